@@ -1,0 +1,169 @@
+"""CPU oracle for the hierarchization of combination grids (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: only the test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The GPU library
+never calls it and shares no code with it.
+
+The arithmetic lives in ``oracle.c`` (plain C, IEEE double precision), which
+follows Algorithm 1 of P. Hupp, "Hierarchization for the Sparse Grid
+Combination Technique" (arXiv:1309.0392), Section 3.  This module only
+marshals numpy arrays into it.
+
+Array convention: a grid of level vector ``(l_0, ..., l_{d-1})`` is a
+C-contiguous float64 array of shape ``(2**l_{d-1}-1, ..., 2**l_0-1)``; the last
+numpy axis is grid axis 0, the fastest-changing index (the paper's x_1).
+
+Parity status: every routine exported here is pinned by ``tests/test_oracle_pins.py``
+(hat basis, linear reproduction, dense hat-evaluation matrices, sine closed form,
+axis-order invariance, dense transpose, brute-force flop counts).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (-O2, no fast-math) into liboracle.so."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lp = ctypes.POINTER(ctypes.c_int64)
+        for name in ("oracle_hierarchize", "oracle_dehierarchize", "oracle_hierarchize_adjoint"):
+            f = getattr(lib, name)
+            f.argtypes = [dp, ctypes.c_int, ip]
+            f.restype = ctypes.c_int
+        for name in ("oracle_hierarchize_axis", "oracle_dehierarchize_axis",
+                     "oracle_hierarchize_adjoint_axis"):
+            f = getattr(lib, name)
+            f.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int]
+            f.restype = ctypes.c_int
+        for name in ("oracle_hierarchize_point", "oracle_dehierarchize_point",
+                     "oracle_hierarchize_adjoint_point"):
+            f = getattr(lib, name)
+            f.argtypes = [dp, ctypes.c_int, ip, lp]
+            f.restype = ctypes.c_double
+        for name in ("oracle_flops_eq1", "oracle_mults_reduced"):
+            f = getattr(lib, name)
+            f.argtypes = [ctypes.c_int, ip]
+            f.restype = ctypes.c_double
+        lib.oracle_num_points.argtypes = [ctypes.c_int, ip]
+        lib.oracle_num_points.restype = ctypes.c_int64
+        _lib = lib
+    return _lib
+
+
+def shape_of(levels) -> tuple:
+    """numpy shape of a grid: reversed (2**l - 1), axis 0 last."""
+    return tuple((1 << int(l)) - 1 for l in reversed(list(levels)))
+
+
+def _levels_arg(levels):
+    lv = [int(l) for l in levels]
+    return (ctypes.c_int * len(lv))(*lv), len(lv)
+
+
+def _check(x: np.ndarray, levels):
+    if x.dtype != np.float64 or not x.flags["C_CONTIGUOUS"]:
+        raise TypeError("oracle works on C-contiguous float64 arrays")
+    if tuple(x.shape) != shape_of(levels):
+        raise ValueError("shape %s does not match levels %s" % (x.shape, tuple(levels)))
+
+
+def _run(name, x, levels, *extra):
+    lib = _load()
+    y = np.array(x, dtype=np.float64, order="C", copy=True)
+    _check(y, levels)
+    lv, d = _levels_arg(levels)
+    rc = getattr(lib, name)(y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), d, lv, *extra)
+    if rc != 0:
+        raise ValueError("%s rejected levels %s" % (name, tuple(levels)))
+    return y
+
+
+def hierarchize(x, levels) -> np.ndarray:
+    """Algorithm 1 on a copy of x (float64)."""
+    return _run("oracle_hierarchize", x, levels)
+
+
+def dehierarchize(x, levels) -> np.ndarray:
+    return _run("oracle_dehierarchize", x, levels)
+
+
+def hierarchize_adjoint(x, levels) -> np.ndarray:
+    return _run("oracle_hierarchize_adjoint", x, levels)
+
+
+def hierarchize_axis(x, levels, axis: int) -> np.ndarray:
+    return _run("oracle_hierarchize_axis", x, levels, int(axis))
+
+
+def dehierarchize_axis(x, levels, axis: int) -> np.ndarray:
+    return _run("oracle_dehierarchize_axis", x, levels, int(axis))
+
+
+def hierarchize_adjoint_axis(x, levels, axis: int) -> np.ndarray:
+    return _run("oracle_hierarchize_adjoint_axis", x, levels, int(axis))
+
+
+_POINT_FN = {
+    "hierarchize": "oracle_hierarchize_point",
+    "dehierarchize": "oracle_dehierarchize_point",
+    "adjoint": "oracle_hierarchize_adjoint_point",
+}
+
+
+def point(op: str, x: np.ndarray, levels, positions) -> np.ndarray:
+    """Outputs of ``op`` at the given points, each computed on its own.
+
+    ``positions`` is an integer array of shape (P, d) of 1-based positions
+    along grid axes 0..d-1.  x is read in place (no copy)."""
+    lib = _load()
+    if x.dtype != np.float64 or not x.flags["C_CONTIGUOUS"]:
+        raise TypeError("oracle works on C-contiguous float64 arrays")
+    if tuple(x.shape) != shape_of(levels):
+        raise ValueError("shape does not match levels")
+    fn = getattr(lib, _POINT_FN[op])
+    lv, d = _levels_arg(levels)
+    pos = np.ascontiguousarray(positions, dtype=np.int64).reshape(-1, d)
+    xp = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    out = np.empty(pos.shape[0], dtype=np.float64)
+    for r in range(pos.shape[0]):
+        out[r] = fn(xp, d, lv, pos[r].ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return out
+
+
+def flops_eq1(levels) -> float:
+    """Corrected Eq. (1) flop count of Algorithm 1."""
+    lv, d = _levels_arg(levels)
+    return _load().oracle_flops_eq1(d, lv)
+
+
+def mults_reduced(levels) -> float:
+    """Multiplications of the reduced-operation variant, M(d, l)."""
+    lv, d = _levels_arg(levels)
+    return _load().oracle_mults_reduced(d, lv)
+
+
+def num_points(levels) -> int:
+    lv, d = _levels_arg(levels)
+    return int(_load().oracle_num_points(d, lv))
