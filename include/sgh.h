@@ -1,0 +1,170 @@
+/*
+ * sgh.h -- C ABI of a gfx950 (AMD Instinct MI355X) library that hierarchizes
+ * the combination grids of the sparse grid combination technique, after
+ * P. Hupp, "Hierarchization for the Sparse Grid Combination Technique",
+ * arXiv:1309.0392.
+ *
+ * Grid model (paper, Section 2, "The Combination Technique"): a combination
+ * grid is completely described by its level vector l = (l_0, ..., l_{d-1});
+ * level 1 is a single point, so axis k holds n_k = 2^{l_k} - 1 interior
+ * points.  Boundary values are zero and are not stored.  Storage is dense and
+ * row major with axis 0 (the paper's x_1) changing fastest (Section 3,
+ * "Unrolling and Vectorization"): the point with 1-based positions
+ * (p_0, ..., p_{d-1}) is element  sum_k (p_k - 1) * S_k,  S_k = prod_{j<k} n_j.
+ *
+ * All entry points are plain C: host pointers to descriptors, device pointers
+ * to grid data, a HIP stream passed as void* (NULL = the default stream).
+ * The caller owns every grid buffer; the library never allocates or frees
+ * caller data.  The library owns plans, their graphs, device task lists and
+ * tuning state.
+ *
+ * Errors: every call returns SGH_OK (0) or a negative SGH_ERR_* code.  All
+ * descriptors of a call are validated on the host before anything is
+ * launched (all or nothing: on a validation error no kernel runs and no data
+ * is touched).  sgh_last_error_message() gives a human-readable detail for
+ * the calling thread's last failure.  Device faults surface, as in HIP, at
+ * the next synchronization of the stream.
+ *
+ * Concurrency: grids of one call must not overlap in memory (SGH_ERR_OVERLAP).
+ * Calls are asynchronous with respect to the host and ordered on `stream`.
+ */
+#ifndef SGH_H
+#define SGH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SGH_MAX_DIM 16   /* the paper's experiments go up to d = 10 (Section 4, Fig. 8) */
+#define SGH_MAX_LEVEL 30 /* per axis; positions fit in int32 */
+
+/* element types of grid data */
+#define SGH_F32 0
+#define SGH_F64 1
+
+/* operations */
+#define SGH_OP_HIERARCHIZE 0   /* nodal -> hierarchical surpluses (Algorithm 1) */
+#define SGH_OP_DEHIERARCHIZE 1 /* hierarchical -> nodal (its exact inverse) */
+#define SGH_OP_ADJOINT 2       /* transpose of the hierarchization map */
+
+/* return codes */
+#define SGH_OK 0
+#define SGH_ERR_ARG (-1)         /* null pointer, bad dim/level/op, size overflow */
+#define SGH_ERR_DTYPE (-2)       /* dtype is neither SGH_F32 nor SGH_F64 */
+#define SGH_ERR_ALIGN (-3)       /* data not aligned to its element size */
+#define SGH_ERR_OVERLAP (-4)     /* two grids of one call share memory */
+#define SGH_ERR_HIP (-5)         /* a HIP runtime call or kernel launch failed */
+#define SGH_ERR_NOMEM (-6)       /* the library could not allocate its own state */
+#define SGH_ERR_UNSUPPORTED (-7) /* valid request that this build does not handle */
+
+/* Grid descriptor.  level[k] for k >= dim is ignored.  data is a device
+ * pointer to prod_k (2^{level[k]} - 1) elements of the given dtype. */
+typedef struct sgh_grid {
+    int32_t dim;                 /* 1 .. SGH_MAX_DIM */
+    int32_t level[SGH_MAX_DIM];  /* 1 .. SGH_MAX_LEVEL */
+    int32_t dtype;               /* SGH_F32 or SGH_F64 */
+    void *data;                  /* device pointer, aligned to the element size */
+} sgh_grid;
+
+/* ---- one-shot transforms (in place) -------------------------------------
+ *
+ * sgh_hierarchize: Algorithm 1 (Section 3).  Along every axis k, each point
+ * turns into its hierarchical surplus: its nodal value minus half of each of
+ * its two hierarchical predecessors (the nearest coarser points to its left
+ * and right in the binary-tree picture of Fig. 3), all read as nodal values,
+ * with zero for a predecessor on the boundary.  Axes commute.
+ *
+ * sgh_dehierarchize: the inverse base change back to the nodal basis, used
+ * after the scatter step of the iterated combination technique (Section 2,
+ * Fig. 2): levels coarse to fine, each point adds half of its (already nodal)
+ * predecessors.
+ *
+ * sgh_hierarchize_adjoint: the transposed map: each point subtracts half of
+ * the values of all points whose predecessor it is (gradient of a loss of the
+ * hierarchized grid with respect to the nodal values).
+ *
+ * grids: host array of n descriptors (n >= 0; n == 0 is a no-op).  Each grid is
+ * transformed in place.  FP64 data is computed in FP64; FP32 data in FP32.
+ */
+int sgh_hierarchize(const sgh_grid *grids, int32_t n, void *stream);
+int sgh_dehierarchize(const sgh_grid *grids, int32_t n, void *stream);
+int sgh_hierarchize_adjoint(const sgh_grid *grids, int32_t n, void *stream);
+
+/* Same as the three above, selected by op (SGH_OP_*). */
+int sgh_transform(int32_t op, const sgh_grid *grids, int32_t n, void *stream);
+
+/* ---- batched plans ------------------------------------------------------
+ *
+ * A plan fixes an operation and a list of grids (shapes, dtypes and data
+ * pointers), builds a device task list and, with SGH_PLAN_GRAPH, captures
+ * all of its launches into one HIP graph.  Grids that fit the on-chip tile
+ * are transformed by one persistent kernel launch that pops whole grids from
+ * the task list (largest first); larger grids get their own launches, captured
+ * in the same graph.  This is the coarse "all combination grids in parallel"
+ * level of the combination technique (Section 2).
+ *
+ * flags: SGH_PLAN_GRAPH   capture into a hipGraph at creation
+ *        SGH_PLAN_AUTOTUNE time candidate tile configurations on scratch
+ *                          buffers at creation and keep the fastest (results
+ *                          are cached per device, op, dtype and level set).
+ * The plan does not own the grid buffers; they must outlive every execute.
+ */
+#define SGH_PLAN_GRAPH 1u
+#define SGH_PLAN_AUTOTUNE 2u
+
+typedef struct sgh_plan sgh_plan;
+
+int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t n, uint32_t flags);
+int sgh_plan_execute(sgh_plan *plan, void *stream);
+/* Repoint the plan to new buffers of identical shapes and dtypes (same n,
+ * same order).  Synchronizes the device first (an execute in flight may still
+ * read the old task list), then rewrites the device task list; the graph is
+ * re-captured only when the plan holds grids too large for the batch kernel. */
+int sgh_plan_set_data(sgh_plan *plan, const sgh_grid *grids, int32_t n);
+/* Writes a short JSON description of the plan (launches, tiles, graph) into
+ * buf (NUL-terminated, truncated to len).  Returns the full length needed. */
+int sgh_plan_describe(const sgh_plan *plan, char *buf, int32_t len);
+void sgh_plan_destroy(sgh_plan *plan);
+
+/* ---- host utilities (no device access) ---------------------------------- */
+
+/* Validates descriptors exactly as the transforms do; touches no memory
+ * behind data.  Returns SGH_OK or the first error. */
+int sgh_validate(const sgh_grid *grids, int32_t n);
+/* Number of stored points of a grid, or -1 on an invalid descriptor. */
+int64_t sgh_num_points(const sgh_grid *grid);
+/* Describes the launch schedule the library would use for one grid (JSON). */
+int sgh_schedule_describe(int32_t op, const sgh_grid *grid, char *buf, int32_t len);
+const char *sgh_error_string(int code);
+const char *sgh_last_error_message(void);
+/* Library version, e.g. "0.1.0". */
+const char *sgh_version(void);
+
+/* Tuning knob: poles of level `level` on strided axes are kept in registers
+ * as dyadic blocks of span 2^block_exponent (the block boundaries are the
+ * coarse points, transformed last; Section 3's binary-tree predecessors of a
+ * block's interior points all lie inside the block).  Applies to schedules
+ * and plans built after the call; 0 restores the default (or the autotuned)
+ * choice.  Returns SGH_ERR_UNSUPPORTED for pairs this build has no kernel for. */
+int sgh_set_pole_block(int32_t level, int32_t block_exponent);
+
+/* ---- measurement support ------------------------------------------------
+ *
+ * With timing on, every kernel the library launches is bracketed by HIP
+ * events recorded on the stream it is launched on; sgh_timing_report sums
+ * their durations per kernel name (it synchronizes those events).  Off by
+ * default; costs two event records per launch when on.  Graph executions are
+ * timed as one unit named "graph".
+ */
+int sgh_timing_enable(int32_t on);
+int sgh_timing_reset(void);
+/* JSON object {name: {"count": c, "ms": total}, ...}; returns needed length. */
+int sgh_timing_report(char *buf, int32_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGH_H */

@@ -1,0 +1,54 @@
+"""Build the gfx950 shared library libsgh.so in-tree with hipcc.
+
+    python -m paper_1309_0392_amd.build
+
+Sources: csrc/sgh_kernels_<f64|f32>_<h|d|a>.hip (device code from the templates
+in csrc/sgh_kernels.inc, one unit per element type and operation, compiled in
+parallel), csrc/sgh_api.cpp (host side, C ABI from include/sgh.h).  Packed FP32 instructions are disabled for all device code.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libsgh.so")
+ARCH = os.environ.get("SGH_OFFLOAD_ARCH", "gfx950")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", INCLUDE, "-I", CSRC, "-Wall"]
+DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+UNITS = [("sgh_kernels_%s_%s.hip" % (t, o), ["-x", "hip"] + DEVICE) for t in ("f64", "f32") for o in "hda"]
+UNITS.append(("sgh_api.cpp", ["-x", "hip"] + DEVICE))
+
+
+def _compile(src: str, flags) -> str:
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC] + COMMON + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
+    subprocess.run(cmd, check=True)
+    return obj
+
+
+def build(verbose: bool = True) -> str:
+    """Compile every unit and link libsgh.so (always rebuilds)."""
+    os.makedirs(BUILD, exist_ok=True)
+    with cf.ThreadPoolExecutor(max_workers=min(len(UNITS), max(1, os.cpu_count() or 1))) as ex:
+        objs = list(ex.map(lambda u: _compile(*u), UNITS))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    subprocess.run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, check=True)
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()
+    sys.exit(0)

@@ -1,0 +1,1058 @@
+// Host side of the hierarchization library: descriptor validation, the
+// per-grid launch schedule, batched plans with HIP-graph capture, the
+// autotuner and event timing.  The C ABI is declared in include/sgh.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "sgh.h"
+#include "sgh_internal.h"
+
+namespace sgh {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(SGH_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t esize_of(int dtype) { return dtype == SGH_F64 ? 8 : 4; }
+
+// ---------------------------------------------------------------------------
+// Validation (all or nothing).
+int validate_one(const sgh_grid &g, int idx, int64_t *npoints) {
+    if (g.dim < 1 || g.dim > SGH_MAX_DIM) return fail(SGH_ERR_ARG, "grid %d: dim %d outside 1..%d", idx, g.dim, SGH_MAX_DIM);
+    if (g.dtype != SGH_F32 && g.dtype != SGH_F64) return fail(SGH_ERR_DTYPE, "grid %d: dtype %d", idx, g.dtype);
+    // the product of 2^l_k - 1 must fit in int64 together with the element size
+    double log2n = 0.0;
+    int64_t n = 1;
+    for (int k = 0; k < g.dim; ++k) {
+        const int L = g.level[k];
+        if (L < 1 || L > SGH_MAX_LEVEL) return fail(SGH_ERR_ARG, "grid %d: level[%d] = %d outside 1..%d", idx, k, L, SGH_MAX_LEVEL);
+        log2n += L;
+    }
+    if (log2n > 58.0) return fail(SGH_ERR_ARG, "grid %d: too many points (|l|_1 = %.0f)", idx, log2n);
+    for (int k = 0; k < g.dim; ++k) n *= (int64_t(1) << g.level[k]) - 1;
+    if (g.data == nullptr) return fail(SGH_ERR_ARG, "grid %d: null data pointer", idx);
+    if (reinterpret_cast<uintptr_t>(g.data) % esize_of(g.dtype) != 0)
+        return fail(SGH_ERR_ALIGN, "grid %d: data %p not aligned to %zu bytes", idx, g.data, esize_of(g.dtype));
+    *npoints = n;
+    return SGH_OK;
+}
+
+int validate_all(const sgh_grid *grids, int32_t n) {
+    if (n < 0) return fail(SGH_ERR_ARG, "negative grid count %d", n);
+    if (n > 0 && grids == nullptr) return fail(SGH_ERR_ARG, "null grid array");
+    std::vector<std::pair<uintptr_t, uintptr_t>> spans;
+    spans.reserve(n);
+    for (int i = 0; i < n; ++i) {
+        int64_t np = 0;
+        int rc = validate_one(grids[i], i, &np);
+        if (rc) return rc;
+        const uintptr_t b = reinterpret_cast<uintptr_t>(grids[i].data);
+        spans.emplace_back(b, b + static_cast<uintptr_t>(np) * esize_of(grids[i].dtype));
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t i = 1; i < spans.size(); ++i)
+        if (spans[i].first < spans[i - 1].second)
+            return fail(SGH_ERR_OVERLAP, "grids overlap in memory at %p", reinterpret_cast<void *>(spans[i].first));
+    return SGH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry: level-1 axes (a single point) are the identity and leave the
+// strides of the other axes unchanged, so they are dropped.
+struct Geom {
+    int d = 0;
+    int L[kMaxDim] = {};
+    int64_t n[kMaxDim] = {};
+    int64_t st[kMaxDim] = {};
+    int64_t N = 1;
+    int dtype = SGH_F64;
+    void *data = nullptr;
+};
+
+Geom make_geom(const sgh_grid &g) {
+    Geom r;
+    r.dtype = g.dtype;
+    r.data = g.data;
+    int64_t st = 1;
+    for (int k = 0; k < g.dim; ++k) {
+        const int L = g.level[k];
+        const int64_t nk = (int64_t(1) << L) - 1;
+        if (L >= 2) {
+            r.L[r.d] = L;
+            r.n[r.d] = nk;
+            r.st[r.d] = st;
+            ++r.d;
+        }
+        st *= nk;
+    }
+    r.N = st;
+    return r;
+}
+
+TileGeom make_tile_geom(const Geom &g, int m) {
+    TileGeom t{};
+    t.m = m;
+    for (int k = 0; k < m; ++k) {
+        t.L[k] = g.L[k];
+        t.n[k] = static_cast<int32_t>(g.n[k]);
+        t.st[k] = static_cast<int32_t>(g.st[k]);
+        t.rst[k] = 1.0f / static_cast<float>(g.st[k]);
+        t.rn[k] = 1.0f / static_cast<float>(g.n[k]);
+    }
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Device properties.
+struct DevInfo {
+    int cus = 256;
+    int lds_per_cu = 160 * 1024;
+    int max_lds_block = 160 * 1024;
+    std::string arch = "gfx950";
+};
+
+DevInfo &dev_info() {
+    static std::mutex mu;
+    static std::map<int, DevInfo> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    DevInfo di;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        di.cus = prop.multiProcessorCount;
+        if (prop.maxSharedMemoryPerMultiProcessor > 0) di.lds_per_cu = static_cast<int>(prop.maxSharedMemoryPerMultiProcessor);
+        if (prop.sharedMemPerBlock > 0) di.max_lds_block = static_cast<int>(prop.sharedMemPerBlock);
+        di.arch = prop.gcnArchName;
+        const size_t colon = di.arch.find(':');
+        if (colon != std::string::npos) di.arch = di.arch.substr(0, colon);
+    }
+    return cache.emplace(dev, di).first->second;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning cache: key -> "v1 v2 ..." (integers).  Filled by the autotuner,
+// persisted to $SGH_AUTOTUNE_CACHE when set.
+std::mutex g_tune_mu;
+std::map<std::string, std::vector<int>> g_tune;
+bool g_tune_loaded = false;
+
+const char *tune_path() { return std::getenv("SGH_AUTOTUNE_CACHE"); }
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *p = tune_path();
+    if (!p) return;
+    std::ifstream in(p);
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream ss(line);
+        std::string key;
+        if (!(ss >> key)) continue;
+        std::vector<int> v;
+        int x;
+        while (ss >> x) v.push_back(x);
+        if (!v.empty()) g_tune[key] = v;
+    }
+}
+
+bool tune_get(const std::string &key, std::vector<int> *out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void tune_put(const std::string &key, const std::vector<int> &v) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tune[key] = v;
+    const char *p = tune_path();
+    if (!p) return;
+    std::ofstream out(p, std::ios::trunc);
+    out << "# sgh autotune cache v1\n";
+    for (auto &kv : g_tune) {
+        out << kv.first;
+        for (int x : kv.second) out << ' ' << x;
+        out << '\n';
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Timing.
+struct TimedLaunch {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_time_mu;
+bool g_timing = false;
+std::vector<TimedLaunch> g_timed;
+std::map<std::string, std::pair<int64_t, double>> g_time_acc;
+
+bool timing_on(hipStream_t s) {
+    if (!g_timing) return false;
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone) return false;
+    return true;
+}
+
+struct TimerScope {
+    bool on = false;
+    hipEvent_t a{}, b{};
+    hipStream_t s{};
+    std::string name;
+    TimerScope(const std::string &nm, hipStream_t st) : s(st), name(nm) {
+        on = timing_on(st);
+        if (!on) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            on = false;
+            return;
+        }
+        (void)hipEventRecord(a, s);
+    }
+    ~TimerScope() {
+        if (!on) return;
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_time_mu);
+        g_timed.push_back({name, a, b});
+    }
+};
+
+void timing_drain_locked() {
+    for (auto &t : g_timed) {
+        float ms = 0.f;
+        if (hipEventSynchronize(t.b) == hipSuccess && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            auto &acc = g_time_acc[t.name];
+            acc.first += 1;
+            acc.second += ms;
+        }
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    g_timed.clear();
+}
+
+// ---------------------------------------------------------------------------
+// Schedule of one grid: a list of launches, applied in order.
+struct Step {
+    enum Kind { TILE, POLE, LEVEL } kind = TILE;
+    TileLaunch tile{};
+    TileTune ttune{};
+    PoleLaunch pole{};
+    PoleTune ptune{};
+    LevelLaunch level{};
+    int axis_lo = 0, axis_hi = 0;  // axes (of the reduced geometry) covered
+};
+
+// Per-level override of the pole block exponent (0 = default), set through
+// sgh_set_pole_block.
+std::mutex g_override_mu;
+int g_pole_B_override[SGH_MAX_LEVEL + 1] = {};
+
+int default_pole_B(int L) {
+    {
+        std::lock_guard<std::mutex> lk(g_override_mu);
+        if (L >= 0 && L <= SGH_MAX_LEVEL && g_pole_B_override[L] > 0) return g_pole_B_override[L];
+    }
+    switch (L) {
+        case 7: return 4;
+        case 8: return 4;
+        case 9: return 5;
+        case 10: return 5;
+        default: return L;
+    }
+}
+
+int pow2_ceil(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Largest number of elements a tile may hold in LDS for this element size.
+int64_t tile_capacity(int dtype) { return dtype == SGH_F64 ? 8192 : 16384; }
+
+void choose_tile_tune(int64_t chunk, TileTune *t) {
+    int nt = 256;
+    if (chunk > 256 * 32) nt = 512;
+    int ept = pow2_ceil(static_cast<int>((chunk + nt - 1) / nt));
+    if (ept < 1) ept = 1;
+    t->nt = nt;
+    t->ept = ept;
+    t->grid = 0;
+}
+
+std::string grid_key(int op, const Geom &g) {
+    std::ostringstream ss;
+    ss << dev_info().arch << ":op" << op << ":dt" << g.dtype << ":l";
+    for (int k = 0; k < g.d; ++k) ss << (k ? "," : "") << g.L[k];
+    return ss.str();
+}
+
+// Build the schedule for one grid; `tuned` overrides (pole B, tile chunk mult).
+std::vector<Step> build_schedule(int op, const Geom &g) {
+    std::vector<Step> steps;
+    if (g.d == 0) return steps;
+    const int64_t cap = tile_capacity(g.dtype);
+    int m = 0;
+    int64_t Sm = 1;
+    while (m < g.d && Sm * g.n[m] <= cap) {
+        Sm *= g.n[m];
+        ++m;
+    }
+    std::vector<int> tuned;
+    const bool have_tuned = tune_get(grid_key(op, g), &tuned);
+    // tile step over axes 0..m-1
+    if (m >= 1) {
+        Step s;
+        s.kind = Step::TILE;
+        s.axis_lo = 0;
+        s.axis_hi = m;
+        s.tile.data = g.data;
+        s.tile.total = g.N;
+        s.tile.g = make_tile_geom(g, m);
+        int64_t target = std::max<int64_t>(Sm, std::min<int64_t>(cap, 2048));
+        if (have_tuned && !tuned.empty() && tuned[0] > 0) target = std::min<int64_t>(cap, Sm * tuned[0]);
+        int64_t mult = std::max<int64_t>(1, target / Sm);
+        if (m == g.d) mult = 1;  // the whole grid is one tile
+        s.tile.chunk = static_cast<int32_t>(Sm * mult);
+        choose_tile_tune(s.tile.chunk, &s.ttune);
+        steps.push_back(s);
+    } else {
+        // axis 0 too long for a tile: per-level fallback
+        for (int lev = 2; lev <= g.L[0]; ++lev) {
+            Step s;
+            s.kind = Step::LEVEL;
+            s.axis_lo = 0;
+            s.axis_hi = 1;
+            s.level.data = g.data;
+            s.level.S = 1;
+            s.level.outer = g.N / g.n[0];
+            s.level.L = g.L[0];
+            s.level.lev = lev;
+            steps.push_back(s);
+        }
+        m = 1;
+    }
+    for (int k = m; k < g.d; ++k) {
+        const int L = g.L[k];
+        int B = default_pole_B(L);
+        bool forced = false;
+        {
+            std::lock_guard<std::mutex> lk(g_override_mu);
+            forced = L <= SGH_MAX_LEVEL && g_pole_B_override[L] > 0;
+        }
+        if (!forced && have_tuned && tuned.size() > static_cast<size_t>(k) && tuned[k] > 0 && pole_supported(L, tuned[k]))
+            B = tuned[k];
+        if (L <= kPoleMaxLevel && pole_supported(L, B)) {
+            Step s;
+            s.kind = Step::POLE;
+            s.axis_lo = k;
+            s.axis_hi = k + 1;
+            s.pole.data = g.data;
+            s.pole.npoles = g.N / g.n[k];
+            s.pole.S = g.st[k];
+            s.pole.L = L;
+            s.pole.B = B;
+            steps.push_back(s);
+        } else {
+            for (int lev = 2; lev <= L; ++lev) {
+                Step s;
+                s.kind = Step::LEVEL;
+                s.axis_lo = k;
+                s.axis_hi = k + 1;
+                s.level.data = g.data;
+                s.level.S = g.st[k];
+                s.level.outer = g.N / (g.n[k] * g.st[k]);
+                s.level.L = L;
+                s.level.lev = lev;
+                steps.push_back(s);
+            }
+        }
+    }
+    // Inverse and transpose: the reverse sequence (per-level steps of one axis
+    // keep the order their operation needs: coarse to fine).
+    if (op != SGH_OP_HIERARCHIZE) {
+        std::vector<Step> rev;
+        for (int k = g.d - 1; k >= 0; --k)
+            for (auto &s : steps)
+                if (s.axis_lo <= k && k < s.axis_hi && (s.axis_hi - 1 == k)) rev.push_back(s);
+        steps.swap(rev);
+    } else {
+        // hierarchization of a long pole runs its levels fine to coarse
+        std::vector<Step> out;
+        size_t i = 0;
+        while (i < steps.size()) {
+            if (steps[i].kind != Step::LEVEL) {
+                out.push_back(steps[i++]);
+                continue;
+            }
+            size_t j = i;
+            while (j < steps.size() && steps[j].kind == Step::LEVEL && steps[j].axis_lo == steps[i].axis_lo) ++j;
+            for (size_t t = j; t > i; --t) out.push_back(steps[t - 1]);
+            i = j;
+        }
+        steps.swap(out);
+    }
+    return steps;
+}
+
+void retarget(std::vector<Step> &steps, void *data) {
+    for (auto &s : steps) {
+        s.tile.data = data;
+        s.pole.data = data;
+        s.level.data = data;
+    }
+}
+
+const char *step_name(const Step &s) {
+    switch (s.kind) {
+        case Step::TILE: return "tile";
+        case Step::POLE: return "pole";
+        default: return "level";
+    }
+}
+
+std::string step_timer_name(int op, int dtype, const Step &s) {
+    std::ostringstream ss;
+    static const char *ops[] = {"hier", "dehier", "adjoint"};
+    ss << ops[op] << "_" << (dtype == SGH_F64 ? "f64" : "f32") << "_" << step_name(s);
+    if (s.kind == Step::POLE) ss << "_L" << s.pole.L;
+    if (s.kind == Step::TILE) ss << "_m" << s.tile.g.m;
+    return ss.str();
+}
+
+hipError_t run_step(int op, int dtype, const Step &s, hipStream_t st) {
+    if (s.kind == Step::TILE && static_cast<int64_t>(s.ttune.nt) * s.ttune.ept < s.tile.chunk) return hipErrorInvalidValue;
+    TimerScope ts(step_timer_name(op, dtype, s), st);
+    switch (s.kind) {
+        case Step::TILE: return launch_tile(op, dtype, s.tile, s.ttune, st);
+        case Step::POLE: return launch_pole(op, dtype, s.pole, s.ptune, st);
+        default: return launch_level(op, dtype, s.level, st);
+    }
+}
+
+std::string describe_steps(int op, const Geom &g, const std::vector<Step> &steps) {
+    std::ostringstream ss;
+    ss << "{\"op\":" << op << ",\"dtype\":" << g.dtype << ",\"points\":" << g.N << ",\"launches\":[";
+    for (size_t i = 0; i < steps.size(); ++i) {
+        const Step &s = steps[i];
+        if (i) ss << ",";
+        ss << "{\"kind\":\"" << step_name(s) << "\",\"axes\":[" << s.axis_lo << "," << s.axis_hi << "]";
+        if (s.kind == Step::TILE)
+            ss << ",\"chunk\":" << s.tile.chunk << ",\"nt\":" << s.ttune.nt << ",\"ept\":" << s.ttune.ept;
+        if (s.kind == Step::POLE) ss << ",\"L\":" << s.pole.L << ",\"B\":" << s.pole.B << ",\"nt\":" << s.ptune.nt;
+        if (s.kind == Step::LEVEL) ss << ",\"L\":" << s.level.L << ",\"lev\":" << s.level.lev;
+        ss << "}";
+    }
+    ss << "],\"hbm_round_trips\":" << [&] {
+        int r = 0;
+        for (auto &s : steps) r += (s.kind == Step::LEVEL) ? 0 : 1;
+        return r;
+    }() << "}";
+    return ss.str();
+}
+
+int copy_out(const std::string &s, char *buf, int32_t len) {
+    if (buf && len > 0) {
+        const size_t n = std::min<size_t>(s.size(), static_cast<size_t>(len - 1));
+        std::memcpy(buf, s.data(), n);
+        buf[n] = 0;
+    }
+    return static_cast<int>(s.size()) + 1;
+}
+
+// ---------------------------------------------------------------------------
+// One-shot transforms: every grid gets its own schedule.
+int transform(int op, const sgh_grid *grids, int32_t n, void *stream) {
+    if (op < 0 || op > 2) return fail(SGH_ERR_ARG, "unknown op %d", op);
+    int rc = validate_all(grids, n);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < n; ++i) {
+        Geom g = make_geom(grids[i]);
+        auto steps = build_schedule(op, g);
+        for (auto &s : steps) {
+            hipError_t e = run_step(op, g.dtype, s, st);
+            if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        }
+    }
+    return SGH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched plans.
+struct BatchGroup {
+    int dtype = SGH_F64;
+    std::vector<int> grid_idx;  // into the plan's grid list, launch order (LPT)
+    BatchTune tune;
+    BatchTask *dev_tasks = nullptr;
+    uint32_t *dev_counters = nullptr;
+};
+
+struct PlanLarge {
+    int grid = 0;
+    Geom geom;
+    std::vector<Step> steps;
+};
+
+int batch_lds_limit(int dtype) { return dtype == SGH_F64 ? 8192 * 8 : 16384 * 4; }
+
+void batch_default_tune(const DevInfo &di, int maxN, int ntasks, int dtype, BatchTune *t, int nt_pref = 0) {
+    int nt = nt_pref ? nt_pref : 256;
+    int ept = pow2_ceil((maxN + nt - 1) / nt);
+    if (ept < 4) ept = 4;
+    while (ept > 32) {
+        nt *= 2;
+        ept = pow2_ceil((maxN + nt - 1) / nt);
+        if (ept < 4) ept = 4;
+    }
+    t->nt = nt;
+    t->ept = ept;
+    t->lds_bytes = std::max<int>(static_cast<int>(maxN * esize_of(dtype)), 16);
+    const int by_lds = std::max(1, di.lds_per_cu / t->lds_bytes);
+    const int by_waves = std::max(1, 32 / (nt / 64));
+    const int per_cu = std::min({by_lds, by_waves, 8});
+    t->nwg = std::max(1, std::min(ntasks, per_cu * di.cus));
+}
+
+}  // namespace
+}  // namespace sgh
+
+struct sgh_plan {
+    int op = 0;
+    uint32_t flags = 0;
+    std::vector<sgh_grid> grids;
+    std::vector<sgh::BatchGroup> groups;
+    std::vector<sgh::PlanLarge> large;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int64_t points = 0;
+};
+
+namespace sgh {
+namespace {
+
+void fill_tasks(const sgh_plan &p, const BatchGroup &bg, std::vector<BatchTask> *tasks) {
+    tasks->clear();
+    for (int gi : bg.grid_idx) {
+        Geom g = make_geom(p.grids[gi]);
+        BatchTask t{};
+        t.data = g.data;
+        t.N = static_cast<int32_t>(g.N);
+        t.g = make_tile_geom(g, g.d);
+        tasks->push_back(t);
+    }
+}
+
+hipError_t plan_launch_all(sgh_plan *p, hipStream_t st) {
+    for (auto &bg : p->groups) {
+        TimerScope ts(std::string(p->op == 0 ? "hier" : p->op == 1 ? "dehier" : "adjoint") +
+                          (bg.dtype == SGH_F64 ? "_f64" : "_f32") + "_batch",
+                      st);
+        hipError_t e = launch_batch(p->op, bg.dtype, bg.dev_tasks, static_cast<int32_t>(bg.grid_idx.size()),
+                                    bg.dev_counters, bg.tune, st);
+        if (e != hipSuccess) return e;
+    }
+    for (auto &lg : p->large)
+        for (auto &s : lg.steps) {
+            hipError_t e = run_step(p->op, lg.geom.dtype, s, st);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
+int plan_capture(sgh_plan *p) {
+    if (p->exec) {
+        (void)hipGraphExecDestroy(p->exec);
+        p->exec = nullptr;
+    }
+    if (p->graph) {
+        (void)hipGraphDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    if (!p->capture_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    }
+    hipError_t e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = plan_launch_all(p, p->capture_stream);
+    e = hipStreamEndCapture(p->capture_stream, &p->graph);
+    if (le != hipSuccess) return hip_fail(le, "launch during capture");
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    return SGH_OK;
+}
+
+// Median time (ms) of `reps` runs of fn on a private stream.
+template <typename F>
+float time_median(F &&fn, hipStream_t st, int reps) {
+    std::vector<float> t;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return 1e30f;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return 1e30f;
+    }
+    for (int r = 0; r < reps + 1; ++r) {
+        (void)hipEventRecord(a, st);
+        if (fn(st) != hipSuccess) {
+            t.assign(1, 1e30f);
+            break;
+        }
+        (void)hipEventRecord(b, st);
+        (void)hipEventSynchronize(b);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (r > 0) t.push_back(ms);  // first run warms up
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    std::sort(t.begin(), t.end());
+    return t.empty() ? 1e30f : t[t.size() / 2];
+}
+
+// Autotune a batch group: candidate workgroup sizes, timed on a scratch copy
+// of the group's shapes (the caller's data is not touched).
+int autotune_group(sgh_plan *p, BatchGroup &bg) {
+    const DevInfo &di = dev_info();
+    std::ostringstream key;
+    key << di.arch << ":batch:op" << p->op << ":dt" << bg.dtype << ":n" << bg.grid_idx.size() << ":h";
+    uint64_t h = 1469598103934665603ull;
+    int maxN = 0;
+    int64_t total = 0;
+    for (int gi : bg.grid_idx) {
+        const sgh_grid &g = p->grids[gi];
+        for (int k = 0; k < g.dim; ++k) h = (h ^ static_cast<uint64_t>(g.level[k] + 31 * k)) * 1099511628211ull;
+        h = (h ^ 0xff) * 1099511628211ull;
+        Geom ge = make_geom(g);
+        maxN = std::max<int>(maxN, static_cast<int>(ge.N));
+        total += ge.N;
+    }
+    key << std::hex << h;
+    std::vector<int> cached;
+    if (tune_get(key.str(), &cached) && cached.size() == 1) {
+        batch_default_tune(di, maxN, static_cast<int>(bg.grid_idx.size()), bg.dtype, &bg.tune, cached[0]);
+        return SGH_OK;
+    }
+    const size_t es = esize_of(bg.dtype);
+    void *scratch = nullptr;
+    hipError_t e = hipMalloc(&scratch, static_cast<size_t>(total) * es);
+    if (e != hipSuccess) return hip_fail(e, "autotune scratch");
+    (void)hipMemset(scratch, 0, static_cast<size_t>(total) * es);
+    std::vector<BatchTask> tasks;
+    fill_tasks(*p, bg, &tasks);
+    int64_t off = 0;
+    for (auto &t : tasks) {
+        t.data = static_cast<char *>(scratch) + off * es;
+        off += t.N;
+    }
+    BatchTask *dtasks = nullptr;
+    uint32_t *dcnt = nullptr;
+    e = hipMalloc(&dtasks, tasks.size() * sizeof(BatchTask));
+    if (e == hipSuccess) e = hipMalloc(&dcnt, 2 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemcpy(dtasks, tasks.data(), tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(dcnt, 0, 2 * sizeof(uint32_t));
+    hipStream_t st = nullptr;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    int best_nt = 256;
+    float best = 1e30f;
+    if (e == hipSuccess) {
+        for (int nt : {128, 256, 512}) {
+            BatchTune t;
+            batch_default_tune(di, maxN, static_cast<int>(tasks.size()), bg.dtype, &t, nt);
+            if (t.nt != nt) continue;
+            const float ms = time_median(
+                [&](hipStream_t s) {
+                    return launch_batch(p->op, bg.dtype, dtasks, static_cast<int32_t>(tasks.size()), dcnt, t, s);
+                },
+                st, 5);
+            if (ms < best) {
+                best = ms;
+                best_nt = nt;
+            }
+        }
+    }
+    if (st) (void)hipStreamDestroy(st);
+    if (dtasks) (void)hipFree(dtasks);
+    if (dcnt) (void)hipFree(dcnt);
+    (void)hipFree(scratch);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    batch_default_tune(di, maxN, static_cast<int>(bg.grid_idx.size()), bg.dtype, &bg.tune, best_nt);
+    tune_put(key.str(), {best_nt});
+    return SGH_OK;
+}
+
+// Autotune the schedule of one large grid: tile chunk multiplier and pole
+// block spans, each timed alone on a scratch grid of the same shape.
+int autotune_large(sgh_plan *p, PlanLarge &lg) {
+    const std::string key = grid_key(p->op, lg.geom);
+    std::vector<int> cached;
+    if (tune_get(key, &cached)) {
+        lg.steps = build_schedule(p->op, lg.geom);
+        return SGH_OK;
+    }
+    const size_t es = esize_of(lg.geom.dtype);
+    void *scratch = nullptr;
+    hipError_t e = hipMalloc(&scratch, static_cast<size_t>(lg.geom.N) * es);
+    if (e != hipSuccess) return hip_fail(e, "autotune scratch");
+    (void)hipMemset(scratch, 0, static_cast<size_t>(lg.geom.N) * es);
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    std::vector<int> choice(static_cast<size_t>(lg.geom.d), 0);
+    if (e == hipSuccess) {
+        Geom sg = lg.geom;
+        sg.data = scratch;
+        auto base = build_schedule(p->op, sg);
+        for (auto &s : base) {
+            if (s.kind == Step::TILE && s.tile.g.m < sg.d) {
+                int64_t Sm = 1;
+                for (int k = 0; k < s.tile.g.m; ++k) Sm *= sg.n[k];
+                float best = 1e30f;
+                int bestm = 0;
+                for (int mult : {1, 2, 4, 8, 16}) {
+                    if (Sm * mult > tile_capacity(sg.dtype)) break;
+                    Step c = s;
+                    c.tile.chunk = static_cast<int32_t>(Sm * mult);
+                    choose_tile_tune(c.tile.chunk, &c.ttune);
+                    const float ms = time_median([&](hipStream_t x) { return run_step(p->op, sg.dtype, c, x); }, st, 3);
+                    if (ms < best) {
+                        best = ms;
+                        bestm = mult;
+                    }
+                }
+                choice[0] = bestm;
+            } else if (s.kind == Step::POLE) {
+                float best = 1e30f;
+                int bestB = s.pole.B;
+                for (int B = 2; B <= s.pole.L; ++B) {
+                    if (!pole_supported(s.pole.L, B)) continue;
+                    Step c = s;
+                    c.pole.B = B;
+                    const float ms = time_median([&](hipStream_t x) { return run_step(p->op, sg.dtype, c, x); }, st, 3);
+                    if (ms < best) {
+                        best = ms;
+                        bestB = B;
+                    }
+                }
+                choice[static_cast<size_t>(s.axis_lo)] = bestB;
+            }
+        }
+    }
+    if (st) (void)hipStreamDestroy(st);
+    (void)hipFree(scratch);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    tune_put(key, choice);
+    lg.steps = build_schedule(p->op, lg.geom);
+    return SGH_OK;
+}
+
+void plan_free(sgh_plan *p) {
+    for (auto &bg : p->groups) {
+        if (bg.dev_tasks) (void)hipFree(bg.dev_tasks);
+        if (bg.dev_counters) (void)hipFree(bg.dev_counters);
+    }
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    delete p;
+}
+
+int plan_upload(sgh_plan *p) {
+    for (auto &bg : p->groups) {
+        std::vector<BatchTask> tasks;
+        fill_tasks(*p, bg, &tasks);
+        hipError_t e = hipMemcpy(bg.dev_tasks, tasks.data(), tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "task upload");
+    }
+    for (auto &lg : p->large) {
+        lg.geom.data = p->grids[lg.grid].data;
+        retarget(lg.steps, lg.geom.data);
+    }
+    return SGH_OK;
+}
+
+}  // namespace
+
+int max_lds_bytes() { return dev_info().max_lds_block; }
+
+}  // namespace sgh
+
+// ---------------------------------------------------------------------------
+// C ABI
+extern "C" {
+
+int sgh_hierarchize(const sgh_grid *grids, int32_t n, void *stream) {
+    return sgh::transform(SGH_OP_HIERARCHIZE, grids, n, stream);
+}
+
+int sgh_dehierarchize(const sgh_grid *grids, int32_t n, void *stream) {
+    return sgh::transform(SGH_OP_DEHIERARCHIZE, grids, n, stream);
+}
+
+int sgh_hierarchize_adjoint(const sgh_grid *grids, int32_t n, void *stream) {
+    return sgh::transform(SGH_OP_ADJOINT, grids, n, stream);
+}
+
+int sgh_transform(int32_t op, const sgh_grid *grids, int32_t n, void *stream) {
+    return sgh::transform(op, grids, n, stream);
+}
+
+int sgh_validate(const sgh_grid *grids, int32_t n) { return sgh::validate_all(grids, n); }
+
+int64_t sgh_num_points(const sgh_grid *grid) {
+    if (!grid) return -1;
+    sgh_grid g = *grid;
+    if (g.data == nullptr) g.data = reinterpret_cast<void *>(uintptr_t(256));  // size query only
+    int64_t n = 0;
+    if (sgh::validate_one(g, 0, &n) != SGH_OK) return -1;
+    return n;
+}
+
+int sgh_schedule_describe(int32_t op, const sgh_grid *grid, char *buf, int32_t len) {
+    if (!grid || op < 0 || op > 2) return sgh::fail(SGH_ERR_ARG, "bad arguments");
+    sgh_grid g = *grid;
+    if (g.data == nullptr) g.data = reinterpret_cast<void *>(uintptr_t(256));
+    int64_t np = 0;
+    int rc = sgh::validate_one(g, 0, &np);
+    if (rc) return rc;
+    sgh::Geom ge = sgh::make_geom(g);
+    return sgh::copy_out(sgh::describe_steps(op, ge, sgh::build_schedule(op, ge)), buf, len);
+}
+
+const char *sgh_error_string(int code) {
+    switch (code) {
+        case SGH_OK: return "success";
+        case SGH_ERR_ARG: return "invalid argument";
+        case SGH_ERR_DTYPE: return "invalid dtype";
+        case SGH_ERR_ALIGN: return "misaligned data pointer";
+        case SGH_ERR_OVERLAP: return "grids overlap";
+        case SGH_ERR_HIP: return "HIP runtime error";
+        case SGH_ERR_NOMEM: return "out of memory";
+        case SGH_ERR_UNSUPPORTED: return "unsupported request";
+        default: return "unknown error";
+    }
+}
+
+const char *sgh_last_error_message(void) { return sgh::g_last_error.c_str(); }
+
+const char *sgh_version(void) { return "0.1.0"; }
+
+int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t n, uint32_t flags) {
+    using namespace sgh;
+    if (!plan) return fail(SGH_ERR_ARG, "null plan pointer");
+    *plan = nullptr;
+    if (op < 0 || op > 2) return fail(SGH_ERR_ARG, "unknown op %d", op);
+    int rc = validate_all(grids, n);
+    if (rc) return rc;
+    std::unique_ptr<sgh_plan, void (*)(sgh_plan *)> p(new (std::nothrow) sgh_plan, plan_free);
+    if (!p) return fail(SGH_ERR_NOMEM, "plan allocation");
+    p->op = op;
+    p->flags = flags;
+    p->grids.assign(grids, grids + n);
+    const DevInfo &di = dev_info();
+    // split: grids that fit one workgroup's LDS go to the batch kernel
+    std::map<int, std::vector<std::pair<int64_t, int>>> small;
+    for (int i = 0; i < n; ++i) {
+        Geom g = make_geom(grids[i]);
+        p->points += g.N;
+        if (g.d == 0) continue;  // all axes of level 1: identity
+        if (g.N * static_cast<int64_t>(esize_of(g.dtype)) <= batch_lds_limit(g.dtype)) {
+            small[g.dtype].push_back({g.N, i});
+        } else {
+            PlanLarge lg;
+            lg.grid = i;
+            lg.geom = g;
+            lg.steps = build_schedule(op, g);
+            p->large.push_back(lg);
+        }
+    }
+    for (auto &kv : small) {
+        BatchGroup bg;
+        bg.dtype = kv.first;
+        auto v = kv.second;
+        // longest processing time first; ties keep list order
+        std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+        for (auto &x : v) bg.grid_idx.push_back(x.second);
+        int maxN = static_cast<int>(v.front().first);
+        batch_default_tune(di, maxN, static_cast<int>(v.size()), bg.dtype, &bg.tune);
+        hipError_t e = hipMalloc(&bg.dev_tasks, v.size() * sizeof(BatchTask));
+        if (e != hipSuccess) return hip_fail(e, "task list");
+        e = hipMalloc(&bg.dev_counters, 2 * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            (void)hipFree(bg.dev_tasks);
+            return hip_fail(e, "counters");
+        }
+        e = hipMemset(bg.dev_counters, 0, 2 * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            (void)hipFree(bg.dev_tasks);
+            (void)hipFree(bg.dev_counters);
+            return hip_fail(e, "counters");
+        }
+        p->groups.push_back(bg);
+    }
+    if (flags & SGH_PLAN_AUTOTUNE) {
+        for (auto &bg : p->groups) {
+            rc = autotune_group(p.get(), bg);
+            if (rc) return rc;
+        }
+        for (auto &lg : p->large) {
+            rc = autotune_large(p.get(), lg);
+            if (rc) return rc;
+        }
+    }
+    rc = plan_upload(p.get());
+    if (rc) return rc;
+    if (flags & SGH_PLAN_GRAPH) {
+        rc = plan_capture(p.get());
+        if (rc) return rc;
+    }
+    *plan = p.release();
+    return SGH_OK;
+}
+
+int sgh_plan_execute(sgh_plan *p, void *stream) {
+    using namespace sgh;
+    if (!p) return fail(SGH_ERR_ARG, "null plan");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p->exec) {
+        TimerScope ts("graph", st);
+        hipError_t e = hipGraphLaunch(p->exec, st);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        return SGH_OK;
+    }
+    hipError_t e = plan_launch_all(p, st);
+    if (e != hipSuccess) return hip_fail(e, "plan launch");
+    return SGH_OK;
+}
+
+int sgh_plan_set_data(sgh_plan *p, const sgh_grid *grids, int32_t n) {
+    using namespace sgh;
+    if (!p) return fail(SGH_ERR_ARG, "null plan");
+    if (n != static_cast<int32_t>(p->grids.size())) return fail(SGH_ERR_ARG, "grid count %d != plan's %zu", n, p->grids.size());
+    int rc = validate_all(grids, n);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        const sgh_grid &a = p->grids[i], &b = grids[i];
+        bool same = a.dim == b.dim && a.dtype == b.dtype;
+        for (int k = 0; same && k < a.dim; ++k) same = a.level[k] == b.level[k];
+        if (!same) return fail(SGH_ERR_ARG, "grid %d: shape or dtype differs from the plan", i);
+    }
+    // the task list may still be read by an execute in flight on any stream
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    for (int i = 0; i < n; ++i) p->grids[i].data = grids[i].data;
+    rc = plan_upload(p);
+    if (rc) return rc;
+    if (p->exec && !p->large.empty()) return plan_capture(p);  // large-grid launches carry pointers
+    return SGH_OK;
+}
+
+int sgh_plan_describe(const sgh_plan *p, char *buf, int32_t len) {
+    using namespace sgh;
+    if (!p) return fail(SGH_ERR_ARG, "null plan");
+    std::ostringstream ss;
+    ss << "{\"op\":" << p->op << ",\"grids\":" << p->grids.size() << ",\"points\":" << p->points
+       << ",\"graph\":" << (p->exec ? "true" : "false") << ",\"batches\":[";
+    for (size_t i = 0; i < p->groups.size(); ++i) {
+        const auto &bg = p->groups[i];
+        if (i) ss << ",";
+        ss << "{\"dtype\":" << bg.dtype << ",\"tasks\":" << bg.grid_idx.size() << ",\"nt\":" << bg.tune.nt
+           << ",\"ept\":" << bg.tune.ept << ",\"workgroups\":" << bg.tune.nwg << ",\"lds_bytes\":" << bg.tune.lds_bytes
+           << "}";
+    }
+    ss << "],\"large\":[";
+    for (size_t i = 0; i < p->large.size(); ++i) {
+        if (i) ss << ",";
+        ss << describe_steps(p->op, p->large[i].geom, p->large[i].steps);
+    }
+    ss << "]}";
+    return copy_out(ss.str(), buf, len);
+}
+
+void sgh_plan_destroy(sgh_plan *p) {
+    if (p) sgh::plan_free(p);
+}
+
+int sgh_set_pole_block(int32_t level, int32_t block_exponent) {
+    using namespace sgh;
+    if (level < 2 || level > SGH_MAX_LEVEL) return fail(SGH_ERR_ARG, "level %d outside 2..%d", level, SGH_MAX_LEVEL);
+    if (block_exponent != 0 && !pole_supported(level, block_exponent))
+        return fail(SGH_ERR_UNSUPPORTED, "no pole kernel for level %d with block exponent %d", level, block_exponent);
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    g_pole_B_override[level] = block_exponent;
+    return SGH_OK;
+}
+
+int sgh_timing_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(sgh::g_time_mu);
+    sgh::g_timing = on != 0;
+    return SGH_OK;
+}
+
+int sgh_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(sgh::g_time_mu);
+    for (auto &t : sgh::g_timed) {
+        (void)hipEventSynchronize(t.b);
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    sgh::g_timed.clear();
+    sgh::g_time_acc.clear();
+    return SGH_OK;
+}
+
+int sgh_timing_report(char *buf, int32_t len) {
+    std::lock_guard<std::mutex> lk(sgh::g_time_mu);
+    sgh::timing_drain_locked();
+    std::ostringstream ss;
+    ss << "{";
+    bool first = true;
+    for (auto &kv : sgh::g_time_acc) {
+        if (!first) ss << ",";
+        first = false;
+        char num[64];
+        std::snprintf(num, sizeof(num), "%.6f", kv.second.second);
+        ss << "\"" << kv.first << "\":{\"count\":" << kv.second.first << ",\"ms\":" << num << "}";
+    }
+    ss << "}";
+    return sgh::copy_out(ss.str(), buf, len);
+}
+
+}  // extern "C"

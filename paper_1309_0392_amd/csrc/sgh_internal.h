@@ -1,0 +1,133 @@
+// Internal declarations shared by the host side (sgh_api.cpp) and the
+// kernels (sgh_kernels.hip) of the hierarchization library.  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sgh.h"
+
+namespace sgh {
+
+constexpr int kMaxDim = SGH_MAX_DIM;
+
+// Longest pole kept entirely in registers by the strided-axis kernel.  A pole
+// of level L is split into 2^(L-B) dyadic blocks of span 2^B.
+constexpr int kPoleMaxLevel = 10;
+
+// Geometry of a tile transformed in LDS: the leading `m` axes (all of level
+// >= 2) of a grid, viewed inside a contiguous run of elements.  Element e of
+// the run has 1-based position  ((e / st[k]) % n[k]) + 1  along slab axis k.
+struct TileGeom {
+    int32_t m;
+    int32_t L[kMaxDim];
+    int32_t n[kMaxDim];
+    int32_t st[kMaxDim];
+    float rst[kMaxDim];  // 1 / st, for exact quotient estimates below 2^15
+    float rn[kMaxDim];   // 1 / n
+};
+
+// One launch over contiguous runs ("chunks") of `chunk` elements each; every
+// chunk holds whole tiles, so it is transformed independently in LDS.
+struct TileLaunch {
+    void *data;
+    int64_t total;  // elements in the grid
+    int32_t chunk;  // elements per chunk (a multiple of the tile size)
+    TileGeom g;
+};
+
+// One grid of a batch, transformed whole in LDS.
+struct BatchTask {
+    void *data;
+    int32_t N;
+    int32_t pad;
+    TileGeom g;
+};
+
+// Strided axis: npoles = outer * S poles of n = 2^L - 1 points at stride S.
+struct PoleLaunch {
+    void *data;
+    int64_t npoles;
+    int64_t S;
+    int32_t L;
+    int32_t B;
+};
+
+// One level of the generic per-level fallback for long poles.
+struct LevelLaunch {
+    void *data;
+    int64_t outer;  // poles per S-run: total / (n * S)
+    int64_t S;
+    int32_t L;
+    int32_t lev;
+};
+
+struct TileTune {
+    int nt = 256;   // threads per workgroup
+    int ept = 4;    // elements per thread (chunk <= nt * ept)
+    int grid = 0;   // workgroups (0 = one per chunk)
+};
+
+struct PoleTune {
+    int nt = 256;
+};
+
+struct BatchTune {
+    int nt = 256;
+    int ept = 8;
+    int nwg = 0;
+    int lds_bytes = 0;
+};
+
+// Launchers per element type and operation (return the first HIP error,
+// hipSuccess otherwise).
+#define SGH_DECLARE_LAUNCHERS(SUF)                                                                    \
+    hipError_t launch_tile_##SUF(const TileLaunch &p, const TileTune &t, hipStream_t s);              \
+    hipError_t launch_pole_##SUF(const PoleLaunch &p, const PoleTune &t, hipStream_t s);              \
+    hipError_t launch_level_##SUF(const LevelLaunch &p, hipStream_t s);                              \
+    hipError_t launch_batch_##SUF(const BatchTask *dev_tasks, int32_t ntasks, uint32_t *dev_counters, \
+                                  const BatchTune &t, hipStream_t s);
+SGH_DECLARE_LAUNCHERS(f64_h)
+SGH_DECLARE_LAUNCHERS(f64_d)
+SGH_DECLARE_LAUNCHERS(f64_a)
+SGH_DECLARE_LAUNCHERS(f32_h)
+SGH_DECLARE_LAUNCHERS(f32_d)
+SGH_DECLARE_LAUNCHERS(f32_a)
+#undef SGH_DECLARE_LAUNCHERS
+
+#define SGH_ROUTE(NAME, ...)                                              \
+    do {                                                                  \
+        if (dtype == SGH_F64) {                                           \
+            if (op == SGH_OP_HIERARCHIZE) return NAME##_f64_h(__VA_ARGS__);   \
+            if (op == SGH_OP_DEHIERARCHIZE) return NAME##_f64_d(__VA_ARGS__); \
+            if (op == SGH_OP_ADJOINT) return NAME##_f64_a(__VA_ARGS__);       \
+        } else if (dtype == SGH_F32) {                                    \
+            if (op == SGH_OP_HIERARCHIZE) return NAME##_f32_h(__VA_ARGS__);   \
+            if (op == SGH_OP_DEHIERARCHIZE) return NAME##_f32_d(__VA_ARGS__); \
+            if (op == SGH_OP_ADJOINT) return NAME##_f32_a(__VA_ARGS__);       \
+        }                                                                 \
+        return hipErrorInvalidValue;                                      \
+    } while (0)
+
+inline hipError_t launch_tile(int op, int dtype, const TileLaunch &p, const TileTune &t, hipStream_t s) {
+    SGH_ROUTE(launch_tile, p, t, s);
+}
+inline hipError_t launch_pole(int op, int dtype, const PoleLaunch &p, const PoleTune &t, hipStream_t s) {
+    SGH_ROUTE(launch_pole, p, t, s);
+}
+inline hipError_t launch_level(int op, int dtype, const LevelLaunch &p, hipStream_t s) {
+    SGH_ROUTE(launch_level, p, s);
+}
+inline hipError_t launch_batch(int op, int dtype, const BatchTask *dev_tasks, int32_t ntasks,
+                               uint32_t *dev_counters, const BatchTune &t, hipStream_t s) {
+    SGH_ROUTE(launch_batch, dev_tasks, ntasks, dev_counters, t, s);
+}
+#undef SGH_ROUTE
+
+bool pole_supported(int L, int B);
+bool tile_ept_supported(int ept);
+bool batch_ept_supported(int ept);
+int max_lds_bytes();
+
+}  // namespace sgh

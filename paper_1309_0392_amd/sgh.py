@@ -1,0 +1,278 @@
+"""Thin Python binding of the C ABI in include/sgh.h (argument marshalling only).
+
+Every transform runs in the HIP kernels of libsgh.so; there is no CPU or
+PyTorch fallback.  If the shared library is missing, importing a function
+raises immediately.
+
+Tensors: a grid of level vector ``levels = (l_0, ..., l_{d-1})`` is a
+contiguous torch tensor on a HIP device with shape
+``(2**l_{d-1}-1, ..., 2**l_0-1)`` (grid axis 0 is the last, contiguous tensor
+axis) and dtype float32 or float64.  Calls are asynchronous on the current
+torch stream (or the stream given).
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+from typing import List, Optional, Sequence
+
+MAX_DIM = 16
+MAX_LEVEL = 30
+F32, F64 = 0, 1
+OP_HIERARCHIZE, OP_DEHIERARCHIZE, OP_ADJOINT = 0, 1, 2
+PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
+
+OK = 0
+ERR_ARG, ERR_DTYPE, ERR_ALIGN, ERR_OVERLAP, ERR_HIP, ERR_NOMEM, ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsgh.so")
+
+
+class SghGrid(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("level", ctypes.c_int32 * MAX_DIM),
+        ("dtype", ctypes.c_int32),
+        ("data", ctypes.c_void_p),
+    ]
+
+
+class SghError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__("%s failed with %d (%s): %s" % (where, code, error_string(code) if _lib else "?", detail))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libsgh.so (ctypes.CDLL).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsgh.so not built: run `python -m paper_1309_0392_amd.build` "
+                               "(or __graft_entry__.build()) first")
+        L = ctypes.CDLL(LIB_PATH)
+        G = ctypes.POINTER(SghGrid)
+        vp, i32, u32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int64
+        sig = {
+            "sgh_hierarchize": ([G, i32, vp], ctypes.c_int),
+            "sgh_dehierarchize": ([G, i32, vp], ctypes.c_int),
+            "sgh_hierarchize_adjoint": ([G, i32, vp], ctypes.c_int),
+            "sgh_transform": ([i32, G, i32, vp], ctypes.c_int),
+            "sgh_plan_create": ([ctypes.POINTER(vp), i32, G, i32, u32], ctypes.c_int),
+            "sgh_plan_execute": ([vp, vp], ctypes.c_int),
+            "sgh_plan_set_data": ([vp, G, i32], ctypes.c_int),
+            "sgh_plan_describe": ([vp, ctypes.c_char_p, i32], ctypes.c_int),
+            "sgh_plan_destroy": ([vp], None),
+            "sgh_validate": ([G, i32], ctypes.c_int),
+            "sgh_num_points": ([G], i64),
+            "sgh_schedule_describe": ([i32, G, ctypes.c_char_p, i32], ctypes.c_int),
+            "sgh_error_string": ([ctypes.c_int], ctypes.c_char_p),
+            "sgh_last_error_message": ([], ctypes.c_char_p),
+            "sgh_version": ([], ctypes.c_char_p),
+            "sgh_timing_enable": ([i32], ctypes.c_int),
+            "sgh_set_pole_block": ([i32, i32], ctypes.c_int),
+            "sgh_timing_reset": ([], ctypes.c_int),
+            "sgh_timing_report": ([ctypes.c_char_p, i32], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def error_string(code: int) -> str:
+    return lib().sgh_error_string(int(code)).decode()
+
+
+def last_error_message() -> str:
+    return lib().sgh_last_error_message().decode()
+
+
+def version() -> str:
+    return lib().sgh_version().decode()
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise SghError(rc, where, last_error_message())
+
+
+# --------------------------------------------------------------- descriptors
+def make_grid(levels: Sequence[int], dtype: int, data_ptr: int) -> SghGrid:
+    g = SghGrid()
+    g.dim = len(levels)
+    for k, l in enumerate(levels):
+        g.level[k] = int(l)
+    g.dtype = int(dtype)
+    g.data = ctypes.c_void_p(int(data_ptr)) if data_ptr else None
+    return g
+
+
+def grid_array(grids: Sequence[SghGrid]):
+    arr = (SghGrid * max(1, len(grids)))()
+    for i, g in enumerate(grids):
+        arr[i] = g
+    return arr
+
+
+def shape_of(levels: Sequence[int]):
+    return tuple((1 << int(l)) - 1 for l in reversed(list(levels)))
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError("grid tensors must be float32 or float64, got %s" % t.dtype)
+
+
+def describe_tensor(t, levels) -> SghGrid:
+    """Descriptor of a torch tensor holding the grid `levels` (validates shape/layout)."""
+    if not t.is_cuda:
+        raise ValueError("grid tensor must live on a HIP device")
+    if tuple(t.shape) != shape_of(levels):
+        raise ValueError("tensor shape %s does not match levels %s (expected %s)"
+                         % (tuple(t.shape), tuple(levels), shape_of(levels)))
+    if not t.is_contiguous():
+        raise ValueError("grid tensor must be contiguous")
+    return make_grid(levels, _dtype_code(t), t.data_ptr())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+def _levels_list(tensors, levels):
+    if levels and isinstance(levels[0], int):
+        levels = [levels] * len(tensors)
+    if len(levels) != len(tensors):
+        raise ValueError("need one level vector per tensor")
+    return levels
+
+
+# ----------------------------------------------------------------- transforms
+def transform(op: int, tensors, levels, stream=None):
+    """Apply op in place to every tensor (one launch schedule per grid)."""
+    if not isinstance(tensors, (list, tuple)):
+        tensors = [tensors]
+        levels = [levels]
+    levels = _levels_list(tensors, levels)
+    descs = [describe_tensor(t, l) for t, l in zip(tensors, levels)]
+    _check(lib().sgh_transform(op, grid_array(descs), len(descs), _stream_handle(stream)), "sgh_transform")
+    return tensors
+
+
+def hierarchize(tensors, levels, stream=None):
+    return transform(OP_HIERARCHIZE, tensors, levels, stream)
+
+
+def dehierarchize(tensors, levels, stream=None):
+    return transform(OP_DEHIERARCHIZE, tensors, levels, stream)
+
+
+def hierarchize_adjoint(tensors, levels, stream=None):
+    return transform(OP_ADJOINT, tensors, levels, stream)
+
+
+# -------------------------------------------------------------------- plans
+class Plan:
+    """A batched plan (sgh_plan_*): one persistent launch for all grids that
+    fit on chip, captured with the launches of larger grids into a HIP graph."""
+
+    def __init__(self, op: int, tensors, levels, graph: bool = True, autotune: bool = False):
+        levels = _levels_list(tensors, levels)
+        self.op = op
+        self.levels = [tuple(int(x) for x in l) for l in levels]
+        self.n = len(tensors)
+        descs = [describe_tensor(t, l) for t, l in zip(tensors, self.levels)]
+        self._arr = grid_array(descs)
+        handle = ctypes.c_void_p()
+        flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0)
+        _check(lib().sgh_plan_create(ctypes.byref(handle), op, self._arr, self.n, flags), "sgh_plan_create")
+        self._h = handle
+
+    def set_data(self, tensors):
+        descs = [describe_tensor(t, l) for t, l in zip(tensors, self.levels)]
+        if len(descs) != self.n:
+            raise ValueError("plan has %d grids, got %d" % (self.n, len(descs)))
+        self._arr = grid_array(descs)
+        _check(lib().sgh_plan_set_data(self._h, self._arr, self.n), "sgh_plan_set_data")
+
+    def execute(self, stream=None):
+        _check(lib().sgh_plan_execute(self._h, _stream_handle(stream)), "sgh_plan_execute")
+
+    def describe(self) -> dict:
+        need = lib().sgh_plan_describe(self._h, None, 0)
+        buf = ctypes.create_string_buffer(max(need, 1))
+        lib().sgh_plan_describe(self._h, buf, len(buf))
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().sgh_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------- host utils
+def validate(grids: Sequence[SghGrid]) -> int:
+    """sgh_validate on raw descriptors (host only); returns the code."""
+    return lib().sgh_validate(grid_array(grids) if grids else None, len(grids))
+
+
+def num_points(levels, dtype: int = F64) -> int:
+    g = make_grid(levels, dtype, 0)
+    return int(lib().sgh_num_points(ctypes.byref(g)))
+
+
+def schedule(op: int, levels, dtype: int = F64) -> dict:
+    """The launch schedule the library uses for one grid (host only)."""
+    g = make_grid(levels, dtype, 0)
+    need = lib().sgh_schedule_describe(op, ctypes.byref(g), None, 0)
+    if need < 0:
+        _check(need, "sgh_schedule_describe")
+    buf = ctypes.create_string_buffer(need)
+    lib().sgh_schedule_describe(op, ctypes.byref(g), buf, len(buf))
+    return json.loads(buf.value.decode())
+
+
+def set_pole_block(level: int, block_exponent: int):
+    """Force the register block span 2**block_exponent for strided poles of `level` (0 = default)."""
+    _check(lib().sgh_set_pole_block(int(level), int(block_exponent)), "sgh_set_pole_block")
+
+
+# POLE_PAIRS: (level, block exponent) pairs of the register-resident pole kernel
+POLE_PAIRS = [(2, 2), (3, 3), (4, 4), (5, 5), (6, 6), (6, 3), (7, 4), (7, 3), (8, 4), (9, 5), (9, 4), (10, 5)]
+
+
+# -------------------------------------------------------------------- timing
+def timing_enable(on: bool = True):
+    _check(lib().sgh_timing_enable(1 if on else 0), "sgh_timing_enable")
+
+
+def timing_reset():
+    _check(lib().sgh_timing_reset(), "sgh_timing_reset")
+
+
+def timing_report() -> dict:
+    need = lib().sgh_timing_report(None, 0)
+    buf = ctypes.create_string_buffer(max(need, 2))
+    lib().sgh_timing_report(buf, len(buf))
+    return json.loads(buf.value.decode() or "{}")

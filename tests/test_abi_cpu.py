@@ -1,0 +1,114 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+symbol the header declares, validates descriptors exactly as documented and
+plans the expected launch schedules."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1309_0392_amd import sgh
+from paper_1309_0392_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sgh.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sgh_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sgh.lib()
+    names = header_functions()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    consts = dict(re.findall(r"#define (SGH_[A-Z0-9_]+) \(?(-?\w+)\)?", text))
+    assert int(consts["SGH_MAX_DIM"]) == sgh.MAX_DIM
+    assert int(consts["SGH_MAX_LEVEL"]) == sgh.MAX_LEVEL
+    assert int(consts["SGH_F32"]) == sgh.F32 and int(consts["SGH_F64"]) == sgh.F64
+    assert int(consts["SGH_ERR_OVERLAP"]) == sgh.ERR_OVERLAP
+    assert int(consts["SGH_PLAN_GRAPH"].rstrip("u")) == sgh.PLAN_GRAPH
+    # struct layout: dim, level[16], dtype, data pointer
+    assert ctypes.sizeof(sgh.SghGrid) == 80 and sgh.SghGrid.data.offset == 72
+
+
+def fake(levels, dtype=sgh.F64, ptr=0x10000):
+    return sgh.make_grid(levels, dtype, ptr)
+
+
+def test_validation_codes():
+    v = sgh.validate
+    assert v([]) == sgh.OK
+    assert v([fake((5, 5))]) == sgh.OK
+    assert v([fake((5, 5), ptr=0)]) == sgh.ERR_ARG                     # null data
+    g = fake((5, 5)); g.dim = 0
+    assert v([g]) == sgh.ERR_ARG                                        # dim 0
+    g = fake((5, 5)); g.dim = 17
+    assert v([g]) == sgh.ERR_ARG                                        # dim > max
+    assert v([fake((0, 3))]) == sgh.ERR_ARG                             # level 0
+    assert v([fake((31,))]) == sgh.ERR_ARG                              # level > 30
+    assert v([fake((20, 20, 20))]) == sgh.ERR_ARG                       # size overflow
+    assert v([fake((5, 5), dtype=7)]) == sgh.ERR_DTYPE
+    assert v([fake((5, 5), ptr=0x10004)]) == sgh.ERR_ALIGN              # f64 at 4-byte offset
+    assert v([fake((5, 5), dtype=sgh.F32, ptr=0x10004)]) == sgh.OK
+    n_bytes = 31 * 31 * 8
+    assert v([fake((5, 5), ptr=0x10000), fake((5, 5), ptr=0x10000 + n_bytes)]) == sgh.OK
+    assert v([fake((5, 5), ptr=0x10000), fake((5, 5), ptr=0x10000 + n_bytes - 8)]) == sgh.ERR_OVERLAP
+    assert sgh.lib().sgh_validate(None, -1) == sgh.ERR_ARG
+    assert sgh.lib().sgh_validate(None, 1) == sgh.ERR_ARG
+    assert "level" in sgh.last_error_message() or "grid" in sgh.last_error_message()
+
+
+def test_transform_rejects_before_launch():
+    """Invalid descriptors come back as codes without touching a device."""
+    bad = sgh.grid_array([fake((5, 5)), fake((0, 5))])
+    assert sgh.lib().sgh_hierarchize(bad, 2, None) == sgh.ERR_ARG
+    assert sgh.lib().sgh_transform(3, bad, 0, None) == sgh.ERR_ARG      # unknown op
+    plan = ctypes.c_void_p()
+    assert sgh.lib().sgh_plan_create(ctypes.byref(plan), 0, bad, 2, 0) == sgh.ERR_ARG
+    assert plan.value is None
+    assert sgh.lib().sgh_plan_create(None, 0, bad, 0, 0) == sgh.ERR_ARG
+
+
+def test_error_strings_and_version():
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -99):
+        assert isinstance(sgh.error_string(code), str) and sgh.error_string(code)
+    assert re.match(r"\d+\.\d+\.\d+", sgh.version())
+
+
+def test_num_points():
+    assert sgh.num_points(W.SMALL_2D) == 961
+    assert sgh.num_points(W.ANISO_3D) == 133302015
+    assert sgh.num_points(W.ANISO_5D) == 118240479
+    assert sgh.num_points((0,)) == -1
+
+
+def test_schedules():
+    s = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D)
+    kinds = [(l["kind"], tuple(l["axes"])) for l in s["launches"]]
+    assert kinds == [("tile", (0, 1)), ("pole", (1, 2)), ("pole", (2, 3))]
+    assert [l.get("L") for l in s["launches"][1:]] == [9, 8]
+    d = sgh.schedule(sgh.OP_DEHIERARCHIZE, W.ANISO_3D)
+    assert [tuple(l["axes"]) for l in d["launches"]] == [(2, 3), (1, 2), (0, 1)]
+    s5 = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_5D)
+    assert [(l["kind"], tuple(l["axes"])) for l in s5["launches"]] == [
+        ("tile", (0, 2)), ("pole", (2, 3)), ("pole", (3, 4)), ("pole", (4, 5))]
+    small = sgh.schedule(sgh.OP_HIERARCHIZE, W.SMALL_2D)
+    assert [(l["kind"], tuple(l["axes"])) for l in small["launches"]] == [("tile", (0, 2))]
+    # level-1 axes are the identity and are dropped
+    assert sgh.schedule(sgh.OP_HIERARCHIZE, (1, 1))["launches"] == []
+    # long poles use the per-level fallback: contiguous l=14 needs 13 levels
+    lv = sgh.schedule(sgh.OP_HIERARCHIZE, (14,))["launches"]
+    assert [l["kind"] for l in lv] == ["level"] * 13
+    assert [l["lev"] for l in lv] == list(range(14, 1, -1))
+    lv = sgh.schedule(sgh.OP_ADJOINT, (3, 12))["launches"]
+    assert lv[0]["kind"] == "level" and [l["lev"] for l in lv[:11]] == list(range(2, 13))
+    assert lv[-1]["kind"] == "tile"

@@ -1,0 +1,70 @@
+"""Differentiation: torch.autograd wrappers around the hierarchization and its
+hand-written adjoint kernel, against torch.autograd.gradcheck, the oracle's
+dense transpose and FP64 central differences."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1309_0392_amd import autograd as AG
+from paper_1309_0392_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("levels", [(3,), (2, 3), (3, 2, 2), (4, 1, 2)])
+def test_gradcheck_single(levels):
+    u = torch.from_numpy(W.uniform(levels, 1)).cuda().requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda v: AG.hierarchize(v, levels), (u,), eps=1e-6, atol=1e-10)
+
+
+def test_gradcheck_batch():
+    lv = [(2, 3), (3,), (2, 2, 2)]
+    us = [torch.from_numpy(W.uniform(l, [5, i])).cuda().requires_grad_(True) for i, l in enumerate(lv)]
+    f = lambda *v: tuple(AG.hierarchize_batch(list(v), lv))
+    assert torch.autograd.gradcheck(f, tuple(us), eps=1e-6, atol=1e-10)
+
+
+def test_backward_is_dense_transpose():
+    levels = (3, 2)
+    n = W.num_points(levels)
+    H = np.stack([oracle.hierarchize(np.eye(n)[j].reshape(W.shape_of(levels)), levels).ravel()
+                  for j in range(n)], axis=1)
+    u = torch.zeros(W.shape_of(levels), dtype=torch.float64, device="cuda", requires_grad=True)
+    G = []
+    for i in range(n):
+        y = AG.hierarchize(u, levels)
+        (g,) = torch.autograd.grad(y.reshape(-1)[i], u)
+        G.append(g.reshape(-1).cpu().numpy())
+    assert np.array_equal(np.stack(G, axis=0), H)
+
+
+def test_combination_loss_gradient_fp32():
+    """loss = sum_l c_l ||H u_l||^2 over the d=4, n=10 set in FP32; gradient 2 c_l H^T H u_l."""
+    lv, coef = W.combination_set()
+    xs = W.combination_values(lv, seed=3, dtype=np.float32)
+    us = [torch.from_numpy(x).cuda().requires_grad_(True) for x in xs]
+    ys = AG.hierarchize_batch(us, lv)
+    loss = sum(c * (y.double() ** 2).sum() for c, y in zip(coef, ys))
+    loss.backward()
+    grads = [u.grad.cpu().numpy().astype(np.float64) for u in us]
+    refs = [2.0 * c * oracle.hierarchize_adjoint(oracle.hierarchize(x.astype(np.float64), l), l)
+            for x, l, c in zip(xs, lv, coef)]
+    gmax = max(float(np.max(np.abs(r))) for r in refs)
+    err = max(float(np.max(np.abs(g - r))) for g, r in zip(grads, refs)) / gmax
+    print("FP32 batched gradient vs FP64 oracle: %.3e (max |g| %.3f)" % (err, gmax), flush=True)
+    assert err <= 2e-6
+    # central differences in FP64 on 64 seeded entries; the loss is quadratic, so
+    # the central difference equals the derivative up to rounding
+    eps = 1e-3
+    for g, flat in W.fd_entries(lv, 64, seed=4):
+        u0 = xs[g].astype(np.float64).ravel()
+        up, um = u0.copy(), u0.copy()
+        up[flat] += eps
+        um[flat] -= eps
+        h = (up[flat] - um[flat])
+        lp = coef[g] * np.sum(oracle.hierarchize(up.reshape(xs[g].shape), lv[g]) ** 2)
+        lm = coef[g] * np.sum(oracle.hierarchize(um.reshape(xs[g].shape), lv[g]) ** 2)
+        fd = (lp - lm) / h
+        assert abs(fd - refs[g].ravel()[flat]) <= 1e-9 * gmax
+        assert abs(fd - grads[g].ravel()[flat]) <= 1e-5 * gmax, (g, flat)

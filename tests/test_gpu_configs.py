@@ -1,0 +1,160 @@
+"""The workloads at full size on the GPU, checked against the oracle.
+
+Full-size grids (1 GB) are too large to run the whole oracle in a test; there
+the check is on sampled output points (computed one by one by the oracle's
+per-point routines) plus the round trip dehierarchize(hierarchize(x)) = x over
+every element.  The combination-technique batch (589 grids) is checked grid by
+grid against the whole-grid oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import OP_NAME, ORACLE, TOL, gpu_run, rel_err
+from paper_1309_0392_amd import sgh
+from paper_1309_0392_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def sample_positions(levels, count, seed):
+    rng = np.random.default_rng(seed)
+    pos = np.stack([rng.integers(1, 1 << l, size=count) for l in levels], axis=1)
+    # always include the corners and the centre (boundary-adjacent predecessors, root)
+    extra = [[1] * len(levels), [(1 << l) - 1 for l in levels], [1 << (l - 1) for l in levels]]
+    return np.concatenate([pos, np.array(extra)], axis=0)
+
+
+def test_small_2d_round_trip():
+    levels = W.SMALL_2D
+    x = W.uniform(levels, 0)
+    h = gpu_run(sgh.OP_HIERARCHIZE, x, levels)
+    assert rel_err(0, x, h, oracle.hierarchize(x, levels)) <= 1e-14
+    back = gpu_run(sgh.OP_DEHIERARCHIZE, h, levels)
+    assert np.max(np.abs(back - x)) <= 1e-14 * np.max(np.abs(x))
+
+
+@pytest.mark.parametrize("name", ["aniso3d", "aniso5d"])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_full_size_sampled(name, dtype):
+    if name == "aniso3d":
+        levels, x = W.ANISO_3D, W.sine_plus_noise(W.ANISO_3D, seed=1)
+    else:
+        levels, x = W.ANISO_5D, W.uniform(W.ANISO_5D, seed=2)
+    x = x.astype(dtype)
+    x64 = x.astype(np.float64)
+    pos = sample_positions(levels, 3000, seed=17)
+    dev = torch.from_numpy(x).cuda()
+    print("full size %s %s: %d points" % (name, dtype.__name__, dev.numel()), flush=True)
+    for op in (sgh.OP_HIERARCHIZE, sgh.OP_ADJOINT, sgh.OP_DEHIERARCHIZE):
+        t = dev.clone()
+        sgh.transform(op, t, levels)
+        torch.cuda.synchronize()
+        got = t.cpu().numpy()
+        idx = tuple((pos[:, k] - 1) for k in reversed(range(len(levels))))
+        ref = oracle.point(OP_NAME[op] if op != sgh.OP_ADJOINT else "adjoint", x64, levels, pos)
+        scale = float(np.max(np.abs(x64)))
+        if op != sgh.OP_HIERARCHIZE:
+            scale = max(scale, float(np.max(np.abs(ref))))
+        err = float(np.max(np.abs(got[idx].astype(np.float64) - ref))) / scale
+        print("  %s sampled err %.3e" % (OP_NAME[op], err), flush=True)
+        assert err <= TOL[dtype]
+        del t
+    # round trip over every element
+    t = dev.clone()
+    sgh.hierarchize(t, levels)
+    sgh.dehierarchize(t, levels)
+    torch.cuda.synchronize()
+    rt = float(torch.max(torch.abs(t - dev)).item()) / float(np.max(np.abs(x64)))
+    print("  round trip err %.3e" % rt, flush=True)
+    assert rt <= (1e-14 if dtype == np.float64 else 4e-6)
+
+
+def combi(dtype):
+    lv, coef = W.combination_set()
+    xs = W.combination_values(lv, seed=3, dtype=dtype)
+    return lv, coef, xs
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("graph", [True, False], ids=["graph", "nograph"])
+def test_combination_batch_plan(dtype, graph):
+    lv, _, xs = combi(dtype)
+    assert len(lv) == 589 and sum(x.size for x in xs) == 980797
+    ts = [torch.from_numpy(x.copy()).cuda() for x in xs]
+    ph = sgh.Plan(sgh.OP_HIERARCHIZE, ts, lv, graph=graph)
+    pd = sgh.Plan(sgh.OP_DEHIERARCHIZE, ts, lv, graph=graph)
+    pa = sgh.Plan(sgh.OP_ADJOINT, ts, lv, graph=graph)
+    desc = ph.describe()
+    assert desc["grids"] == 589 and desc["points"] == 980797 and desc["large"] == []
+    assert desc["graph"] == graph
+    refs = {op: [ORACLE[op](x.astype(np.float64), l) for x, l in zip(xs, lv)] for op in ORACLE}
+    scratch = torch.randn(1 << 20, device="cuda")
+    for rep in range(3):
+        for plan, op in ((ph, sgh.OP_HIERARCHIZE), (pd, sgh.OP_DEHIERARCHIZE), (pa, sgh.OP_ADJOINT)):
+            for t, x in zip(ts, xs):
+                t.copy_(torch.from_numpy(x))
+            plan.execute()
+            scratch.mul_(1.0001)  # unrelated eager work between replays
+            torch.cuda.synchronize()
+            worst = 0.0
+            for t, x, r in zip(ts, xs, refs[op]):
+                worst = max(worst, rel_err(op, x.astype(np.float64), t.cpu().numpy(), r))
+            print("rep %d %s %s graph=%s worst err %.3e" % (rep, OP_NAME[op], dtype.__name__, graph, worst), flush=True)
+            assert worst <= TOL[dtype]
+    for p in (ph, pd, pa):
+        p.close()
+
+
+def test_batch_equals_per_grid_and_set_data():
+    lv, _, xs = combi(np.float64)
+    ts = [torch.from_numpy(x.copy()).cuda() for x in xs]
+    per = [torch.from_numpy(x.copy()).cuda() for x in xs]
+    plan = sgh.Plan(sgh.OP_HIERARCHIZE, ts, lv, graph=True)
+    plan.execute()
+    for t, l in zip(per, lv):
+        sgh.hierarchize(t, l)
+    torch.cuda.synchronize()
+    for a, b in zip(ts, per):
+        assert torch.equal(a, b)
+    # repoint to fresh buffers in shuffled memory order
+    order = np.random.default_rng(0).permutation(len(lv))
+    fresh = [None] * len(lv)
+    for i in order:
+        fresh[i] = torch.from_numpy(xs[i].copy()).cuda()
+    plan.set_data(fresh)
+    plan.execute()
+    torch.cuda.synchronize()
+    for a, b in zip(fresh, per):
+        assert torch.equal(a, b)
+    plan.close()
+
+
+def test_plan_with_large_and_mixed_grids():
+    lv = [(10, 9, 4), (3, 3), (2, 5, 1), (7, 7)]
+    dts = [np.float64, np.float32, np.float64, np.float64]
+    xs = [W.uniform(l, [40, i], d) for i, (l, d) in enumerate(zip(lv, dts))]
+    ts = [torch.from_numpy(x.copy()).cuda() for x in xs]
+    for op in ORACLE:
+        for t, x in zip(ts, xs):
+            t.copy_(torch.from_numpy(x))
+        plan = sgh.Plan(op, ts, lv, graph=True)
+        d = plan.describe()
+        assert len(d["large"]) == 2 and sum(b["tasks"] for b in d["batches"]) == 2
+        plan.execute()
+        torch.cuda.synchronize()
+        for t, x, l, dt in zip(ts, xs, lv, dts):
+            ref = ORACLE[op](x.astype(np.float64), l)
+            assert rel_err(op, x.astype(np.float64), t.cpu().numpy(), ref) <= TOL[dt], (OP_NAME[op], l)
+        plan.close()
+
+
+def test_autotuned_plan_matches():
+    lv, _, xs = combi(np.float32)
+    ts = [torch.from_numpy(x.copy()).cuda() for x in xs]
+    plan = sgh.Plan(sgh.OP_HIERARCHIZE, ts, lv, graph=True, autotune=True)
+    plan.execute()
+    torch.cuda.synchronize()
+    for t, x, l in zip(ts, xs, lv):
+        assert rel_err(0, x.astype(np.float64), t.cpu().numpy(), oracle.hierarchize(x.astype(np.float64), l)) <= 2e-6
+    plan.close()

@@ -1,0 +1,153 @@
+"""GPU parity: every kernel path against the CPU oracle, element by element.
+
+Shapes are chosen so that each launch schedule of the library runs: whole grid
+in one LDS tile, LDS tile over the leading axes plus register-resident strided
+poles (every supported block split), the per-level fallback for long poles,
+level-1 axes, and up to 16 dimensions."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import OP_NAME, ORACLE, TOL, gpu_run, rel_err
+from paper_1309_0392_amd import sgh
+from paper_1309_0392_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+OPS = [sgh.OP_HIERARCHIZE, sgh.OP_DEHIERARCHIZE, sgh.OP_ADJOINT]
+DTYPES = [np.float64, np.float32]
+
+SHAPES = [
+    # whole grid in one tile
+    (1,), (2,), (5,), (13,), (5, 5), (3, 2, 4), (2, 2, 2, 2, 2, 2), (1, 3, 1, 2), (10, 3),
+    # leading-axes tile + strided poles (FP64 tile capacity 8192 points)
+    (7, 7), (10, 2), (10, 4, 3), (4, 4, 6), (3, 3, 3, 9), (5, 9), (2, 10, 2), (6, 8), (4, 10), (3, 5, 2, 5),
+    # per-level fallback: contiguous axis too long for a tile, strided axis too long for registers
+    (14,), (3, 11), (2, 12, 2),
+    # many dimensions, and the 10-d anisotropic stress shape (first axis grows, others 3 points)
+    (2,) * 10, (6,) + (2,) * 9, (2, 2, 2, 2, 2, 2) + (1,) * 9 + (3,),
+]
+
+
+def ids(v):
+    return "l" + "-".join(map(str, v))
+
+
+@pytest.mark.parametrize("levels", SHAPES, ids=ids)
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_parity_all_ops(levels, dtype):
+    x = W.uniform(levels, [21, len(levels)], dtype)
+    x64 = x.astype(np.float64)
+    for op in OPS:
+        ref = ORACLE[op](x64, levels)
+        got = gpu_run(op, x, levels)
+        err = rel_err(op, x64, got, ref)
+        print("levels=%s dtype=%s op=%s err=%.3e" % (levels, dtype.__name__, OP_NAME[op], err), flush=True)
+        assert err <= TOL[dtype], (OP_NAME[op], err)
+
+
+@pytest.mark.parametrize("L,B", sgh.POLE_PAIRS)
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_every_pole_block_split(L, B, dtype):
+    """Every (level, block) variant of the register-resident strided kernel, at a
+    stride large enough for full coalescing and at a tiny stride (ragged rows)."""
+    sgh.set_pole_block(L, B)
+    cap = 8192 if dtype == np.float64 else 16384  # points of the leading-axes LDS tile
+    leads = [(12,) if dtype == np.float64 else (13,)]  # wide stride: 4095 / 8191 lanes per row
+    if 31 * ((1 << L) - 1) > cap:
+        leads.append((5,))  # stride 31: rows shorter than a wavefront
+    try:
+        for lead in leads:
+            levels = lead + (L,)
+            sched = sgh.schedule(sgh.OP_HIERARCHIZE, levels, sgh.F64 if dtype == np.float64 else sgh.F32)
+            x = W.uniform(levels, [22, L, B], dtype)
+            x64 = x.astype(np.float64)
+            for op in OPS:
+                ref = ORACLE[op](x64, levels)
+                got = gpu_run(op, x, levels)
+                err = rel_err(op, x64, got, ref)
+                print("L=%d B=%d lead=%s op=%s err=%.3e sched=%s" % (L, B, lead, OP_NAME[op], err,
+                      [l["kind"] for l in sched["launches"]]), flush=True)
+                assert [l["kind"] for l in sched["launches"]] == ["tile", "pole"]
+                assert sched["launches"][1]["B"] == B
+                assert err <= TOL[dtype], (OP_NAME[op], err)
+    finally:
+        sgh.set_pole_block(L, 0)
+
+
+def test_fp64_matches_oracle_bitwise_on_pole_and_tile_paths():
+    """Same update order as the oracle, and 0.5*a is exact: FP64 results agree bit for bit."""
+    for levels in [(7, 7), (10, 4, 3), (5, 9), (3, 11)]:
+        x = W.uniform(levels, 5)
+        for op in OPS:
+            got = gpu_run(op, x, levels)
+            assert np.array_equal(got, ORACLE[op](x, levels)), (levels, OP_NAME[op])
+
+
+def test_deterministic_and_in_place_safe():
+    levels = (9, 6, 5)
+    x = W.uniform(levels, 3)
+    a = gpu_run(sgh.OP_HIERARCHIZE, x, levels)
+    b = gpu_run(sgh.OP_HIERARCHIZE, x, levels)
+    assert np.array_equal(a, b)
+
+
+def test_hat_function_exact_in_both_precisions():
+    levels = (6, 5, 4)
+    rng = np.random.default_rng(8)
+    for dtype in DTYPES:
+        for _ in range(4):
+            m = [int(rng.integers(1, l + 1)) for l in levels]
+            j = [int(2 * rng.integers(0, 1 << (mk - 1)) + 1) for mk in m]
+            x = np.ones(W.shape_of(levels))
+            for k, (l, mk, jk) in enumerate(zip(levels, m, j)):
+                c = np.arange(1, 1 << l) / float(1 << l)
+                v = np.maximum(0.0, 1.0 - np.abs(c * (1 << mk) - jk))
+                view = [1] * len(levels)
+                view[len(levels) - 1 - k] = v.size
+                x = x * v.reshape(view)
+            got = gpu_run(sgh.OP_HIERARCHIZE, x.astype(dtype), levels)
+            expect = np.zeros_like(x)
+            expect[tuple((jk << (l - mk)) - 1 for l, mk, jk in reversed(list(zip(levels, m, j))))] = 1.0
+            assert np.array_equal(got.astype(np.float64), expect)
+
+
+def test_many_grids_in_one_call_and_empty_call():
+    lv = [(3, 4), (7, 7), (2, 2, 2), (5,)]
+    xs = [W.uniform(l, [30, i]) for i, l in enumerate(lv)]
+    ts = [torch.from_numpy(a.copy()).cuda() for a in xs]
+    sgh.hierarchize(ts, lv)
+    sgh.hierarchize([], [])
+    torch.cuda.synchronize()
+    for a, t, l in zip(xs, ts, lv):
+        assert np.array_equal(t.cpu().numpy(), oracle.hierarchize(a, l))
+
+
+def test_invalid_call_launches_nothing():
+    """All-or-nothing validation: one bad descriptor -> error code, no grid touched."""
+    good = torch.from_numpy(W.uniform((5, 5), 1)).cuda()
+    before = good.clone()
+    other = torch.zeros(100, dtype=torch.float64, device="cuda")
+    descs = [sgh.describe_tensor(good, (5, 5)),
+             sgh.make_grid((5, 5), sgh.F64, other.data_ptr() + 4)]        # misaligned
+    rc = sgh.lib().sgh_hierarchize(sgh.grid_array(descs), 2, None)
+    assert rc == sgh.ERR_ALIGN
+    overlap = [sgh.describe_tensor(good, (5, 5)), sgh.make_grid((3,), sgh.F64, good.data_ptr() + 8)]
+    assert sgh.lib().sgh_hierarchize(sgh.grid_array(overlap), 2, None) == sgh.ERR_OVERLAP
+    torch.cuda.synchronize()
+    assert torch.equal(good, before)
+    # the library stays usable
+    sgh.hierarchize(good, (5, 5))
+    torch.cuda.synchronize()
+    assert np.array_equal(good.cpu().numpy(), oracle.hierarchize(before.cpu().numpy(), (5, 5)))
+
+
+def test_shape_checks_in_binding():
+    t = torch.zeros((31, 31), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        sgh.hierarchize(t, (5, 4))
+    with pytest.raises(ValueError):
+        sgh.hierarchize(t.t(), (5, 5))
+    with pytest.raises(TypeError):
+        sgh.hierarchize(t.half(), (5, 5))
