@@ -1,0 +1,228 @@
+"""Benchmark: grid points hierarchized per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f64|f32]
+                    [--no-cpu-baseline] [--no-extras]
+
+One step is one in-place hierarchization (all axes) of the d=3 anisotropic
+grid of level (10, 9, 8): 1023 x 511 x 255 = 133,302,015 points, 1.07 GB in
+FP64, values prod_k sin(pi x_k) + 0.01 N(0,1) (seed 1), already resident in
+HBM.  The step is timed with HIP events on the launch stream; every library
+kernel is also bracketed by its own events (sgh_timing_*), which gives the
+per-kernel durations behind the roofline figure.
+
+Prints one JSON line.  `value` is points/s of the whole job (one GPU).
+Extra fields: the inverse and the transpose on the same grid, the batched
+combination-technique set (589 grids, one graph-captured persistent launch)
+versus a loop of per-grid calls, a measured copy roof, the roofline of the
+dominant kernel and the CPU oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+METRIC = "grid points hierarchized/s + achieved HBM GB/s vs peak; batched vs per-grid speedup"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only copy a buffer of the workload's size (reference kernel for HBM counters)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1309_0392_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".inc", ".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it
+    was taken with the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if data.get("source_hash") != kernel_source_hash():
+        return None
+    entry = data.get("kernels", {}).get(kernel)
+    return None if entry is None else entry.get("bytes_per_launch")
+
+
+def time_region(torch, fn, steps):
+    s = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(s)
+    for _ in range(steps):
+        fn()
+    b.record(s)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the transform of one grid, or of a combination set, "
+              "runs on a single device here (multi-GPU sharding is described in DESIGN.md, not built); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1309_0392_amd import sgh
+    from paper_1309_0392_amd import workloads as W
+
+    sgh.lib()  # fails loudly if the HIP library is not built
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    dt_np = np.float64 if args.dtype == "f64" else np.float32
+    esize = 8 if args.dtype == "f64" else 4
+    levels = W.ANISO_3D
+    N = W.num_points(levels)
+
+    if args.copy_only:
+        a = torch.empty(N, dtype=torch.float64 if esize == 8 else torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        ms = time_region(torch, lambda: b.copy_(a), 10) / 10
+        print(json.dumps({"copy_bytes_read": N * esize, "copy_bytes_written": N * esize, "copies": 10,
+                          "copy_GBps": 2.0 * N * esize / (ms * 1e-3) / 1e9}))
+        return
+
+    t0 = time.time()
+    x_host = W.sine_plus_noise(levels, seed=1).astype(dt_np, copy=False)
+    x = torch.from_numpy(x_host).to(dev)
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+
+    step = lambda: sgh.hierarchize(x, levels)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    sgh.timing_reset()
+    sgh.timing_enable(True)
+    ms_total = time_region(torch, step, args.steps)
+    report = sgh.timing_report()
+    sgh.timing_enable(False)
+    ms_per_step = ms_total / args.steps
+    value = N / (ms_per_step * 1e-3)
+
+    # dominant kernel: the one with the largest share of the timed region
+    dom = max(report.items(), key=lambda kv: kv[1]["ms"])
+    dom_name, dom_stats = dom[0], dom[1]
+    dom_ms = dom_stats["ms"] / dom_stats["count"]
+    algo_bytes = 2.0 * N * esize  # each launch reads and writes every point once
+    achieved = algo_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom_name)
+    kernels = {k: {"launches": v["count"], "avg_ms": v["ms"] / v["count"],
+                   "GBps_algorithmic": algo_bytes / (v["ms"] / v["count"] * 1e-3) / 1e9}
+               for k, v in report.items()}
+    launches_per_step = sum(v["count"] for v in report.values()) / args.steps
+    whole_GBps = 2.0 * N * esize / (ms_per_step * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "hierarchize d=3 level (10,9,8): 1023x511x255 = %d points, %s, "
+                               "prod sin(pi x_k) + 0.01 N(0,1), seed 1" % (N, args.dtype.upper()),
+                   "levels": list(levels), "points": N, "bytes": N * esize},
+        "hbm_GBps_one_round_trip": whole_GBps,
+        "hbm_frac_of_peak_one_round_trip": whole_GBps / HBM_PEAK_GBS,
+        "launches_per_step": launches_per_step,
+        "kernels": kernels,
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": algo_bytes,
+                     "avg_launch_ms": dom_ms},
+    }
+
+    if not args.no_extras:
+        extras = {}
+        # inverse and transpose on the same grid
+        for name, op in (("dehierarchize", sgh.OP_DEHIERARCHIZE), ("adjoint", sgh.OP_ADJOINT)):
+            f = lambda op=op: sgh.transform(op, x, levels)
+            f()
+            ms = time_region(torch, f, max(3, args.steps // 2)) / max(3, args.steps // 2)
+            extras[name + "_points_per_s"] = N / (ms * 1e-3)
+        # measured copy roof on the same bytes
+        y = torch.empty_like(x)
+        y.copy_(x)
+        ms = time_region(torch, lambda: y.copy_(x), 10) / 10
+        extras["copy_GBps"] = 2.0 * N * esize / (ms * 1e-3) / 1e9
+        del y
+        # batched combination technique set vs per-grid calls
+        lv, _ = W.combination_set()
+        for bdt, bname in ((np.float64, "f64"), (np.float32, "f32")):
+            xs = [torch.from_numpy(a).to(dev) for a in W.combination_values(lv, seed=3, dtype=bdt)]
+            npts = sum(t.numel() for t in xs)
+            plan = sgh.Plan(sgh.OP_HIERARCHIZE, xs, lv, graph=True)
+            plan.execute()
+            ms_plan = time_region(torch, plan.execute, 50) / 50
+
+            def loop():
+                for t, l in zip(xs, lv):
+                    sgh.hierarchize(t, l)
+            loop()
+            ms_loop = time_region(torch, loop, 5) / 5
+            extras["batch_" + bname] = {"grids": len(lv), "points": npts, "plan_ms": ms_plan,
+                                        "points_per_s": npts / (ms_plan * 1e-3),
+                                        "per_grid_loop_ms": ms_loop, "speedup_vs_per_grid": ms_loop / ms_plan,
+                                        "plan": plan.describe()["batches"]}
+            plan.close()
+        out["extras"] = extras
+
+    if not args.no_cpu_baseline:
+        import oracle
+        reps = 3
+        times = []
+        for _ in range(reps):
+            t = time.time()
+            oracle.hierarchize(x_host.astype(np.float64, copy=False), levels)
+            times.append(time.time() - t)
+        med = sorted(times)[reps // 2]
+        out["cpu_baseline"] = {"value": N / med, "unit": "points/s", "cores": 1, "kind": "oracle",
+                               "sample": "the full (10,9,8) grid, FP64, hierarchized by the C oracle "
+                                         "(Algorithm 1, single thread) %d times, median; includes the "
+                                         "oracle's input copy" % reps}
+    out["input_generation_s"] = gen_s
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
