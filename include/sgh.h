@@ -150,6 +150,14 @@ const char *sgh_version(void);
  * choice.  Returns SGH_ERR_UNSUPPORTED for pairs this build has no kernel for. */
 int sgh_set_pole_block(int32_t level, int32_t block_exponent);
 
+/* Schedule switch: level 1 (default) fuses the leading LDS-tile axes with one
+ * strided axis walked in registers into a single launch (one HBM round trip
+ * for both); level 0 keeps one launch for the tile axes and one per strided
+ * axis.  Axes commute (Algorithm 1's outer loop may take the dimensions in any
+ * order), so both give the same map.  Applies to schedules and plans built
+ * after the call. */
+int sgh_set_fusion(int32_t level);
+
 /* ---- measurement support ------------------------------------------------
  *
  * With timing on, every kernel the library launches is bracketed by HIP

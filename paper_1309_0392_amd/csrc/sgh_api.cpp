@@ -268,31 +268,56 @@ void timing_drain_locked() {
 // ---------------------------------------------------------------------------
 // Schedule of one grid: a list of launches, applied in order.
 struct Step {
-    enum Kind { TILE, POLE, LEVEL } kind = TILE;
+    enum Kind { TILE, POLE, LEVEL, TW } kind = TILE;
     TileLaunch tile{};
     TileTune ttune{};
     PoleLaunch pole{};
     PoleTune ptune{};
     LevelLaunch level{};
-    int axis_lo = 0, axis_hi = 0;  // axes (of the reduced geometry) covered
+    TWLaunch tw{};
+    std::vector<int> axes;  // axes (of the reduced geometry) this launch transforms
+    int key = 0;            // largest axis covered; orders the inverse/transpose schedule
 };
 
 // Per-level override of the pole block exponent (0 = default), set through
-// sgh_set_pole_block.
+// sgh_set_pole_block, and the fusion switch set through sgh_set_fusion.
 std::mutex g_override_mu;
 int g_pole_B_override[SGH_MAX_LEVEL + 1] = {};
+int g_fusion = 1;
+
+int pole_B_override(int L) {
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    return (L >= 0 && L <= SGH_MAX_LEVEL) ? g_pole_B_override[L] : 0;
+}
+
+int fusion_level() {
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    return g_fusion;
+}
 
 int default_pole_B(int L) {
-    {
-        std::lock_guard<std::mutex> lk(g_override_mu);
-        if (L >= 0 && L <= SGH_MAX_LEVEL && g_pole_B_override[L] > 0) return g_pole_B_override[L];
-    }
+    const int o = pole_B_override(L);
+    if (o > 0) return o;
     switch (L) {
         case 7: return 4;
         case 8: return 4;
         case 9: return 5;
         case 10: return 5;
         default: return L;
+    }
+}
+
+// Block exponent of a walked axis in the fused kernel (small register state).
+int default_tw_B(int L) {
+    switch (L) {
+        case 2: return 2;
+        case 3: return 3;
+        case 4: return 2;
+        case 5: return 3;
+        case 6: return 3;
+        case 7: return 4;
+        case 8: return 4;
+        default: return 0;
     }
 }
 
@@ -322,10 +347,40 @@ std::string grid_key(int op, const Geom &g) {
     return ss.str();
 }
 
-// Build the schedule for one grid; `tuned` overrides (pole B, tile chunk mult).
-std::vector<Step> build_schedule(int op, const Geom &g) {
-    std::vector<Step> steps;
-    if (g.d == 0) return steps;
+// Choices a schedule is built from.  walk: -1 = default, -2 = no fused walk,
+// k >= 0 = walk axis k.  tile_mult: tiles per LDS chunk (0 = default).
+// pole_code[k]: B * 1000 + workgroup size for strided axis k (0 = default).
+struct SchedOpts {
+    int walk = -1;
+    int tile_mult = 0;
+    std::vector<int> pole_code;
+};
+
+// Tuning-cache layout per grid: [tile_mult, pole_code_1 .. pole_code_{d-1}, walk code]
+// with walk code 0 = default, 1 = none, 2 + k = axis k.
+SchedOpts opts_from_tuned(const Geom &g, const std::vector<int> &t) {
+    SchedOpts o;
+    o.pole_code.assign(static_cast<size_t>(g.d), 0);
+    if (!t.empty()) o.tile_mult = t[0];
+    for (int k = 1; k < g.d && static_cast<size_t>(k) < t.size(); ++k) o.pole_code[static_cast<size_t>(k)] = t[static_cast<size_t>(k)];
+    if (t.size() > static_cast<size_t>(g.d)) {
+        const int w = t[static_cast<size_t>(g.d)];
+        o.walk = w == 0 ? -1 : (w == 1 ? -2 : w - 2);
+    }
+    return o;
+}
+
+std::vector<int> tuned_from_opts(const Geom &g, const SchedOpts &o) {
+    std::vector<int> t(static_cast<size_t>(g.d) + 1, 0);
+    t[0] = o.tile_mult;
+    for (int k = 1; k < g.d; ++k)
+        t[static_cast<size_t>(k)] = static_cast<size_t>(k) < o.pole_code.size() ? o.pole_code[static_cast<size_t>(k)] : 0;
+    t[static_cast<size_t>(g.d)] = o.walk == -1 ? 0 : (o.walk == -2 ? 1 : o.walk + 2);
+    return t;
+}
+
+// Number of leading axes that fit one LDS tile, and the tile size.
+int tile_axes(const Geom &g, int64_t *Sm_out) {
     const int64_t cap = tile_capacity(g.dtype);
     int m = 0;
     int64_t Sm = 1;
@@ -333,19 +388,73 @@ std::vector<Step> build_schedule(int op, const Geom &g) {
         Sm *= g.n[m];
         ++m;
     }
-    std::vector<int> tuned;
-    const bool have_tuned = tune_get(grid_key(op, g), &tuned);
-    // tile step over axes 0..m-1
-    if (m >= 1) {
+    *Sm_out = Sm;
+    return m;
+}
+
+// Can axis w (>= m) be walked by the fused kernel over a tile of Sm points?
+bool walk_ok(const Geom &g, int m, int64_t Sm, int w) {
+    if (m < 1 || w < m || w >= g.d || Sm > 4 * kTWThreads) return false;
+    const int L = g.L[w];
+    const int ept = Sm <= kTWThreads ? 1 : (Sm <= 2 * kTWThreads ? 2 : 4);
+    if (!tw_supported(L, default_tw_B(L), ept)) return false;
+    // the pencil's byte offsets must fit the 32-bit buffer window
+    const int64_t bytes = g.n[w] * g.st[w] * static_cast<int64_t>(esize_of(g.dtype));
+    return bytes < (int64_t(1) << 32) - 1;
+}
+
+// Walk candidates of a grid (largest stride first).
+std::vector<int> walk_candidates(const Geom &g) {
+    std::vector<int> c;
+    int64_t Sm = 1;
+    const int m = tile_axes(g, &Sm);
+    if (m >= g.d) return c;
+    for (int w = g.d - 1; w >= m; --w)
+        if (walk_ok(g, m, Sm, w)) c.push_back(w);
+    return c;
+}
+
+std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o) {
+    std::vector<Step> steps;
+    if (g.d == 0) return steps;
+    const int64_t cap = tile_capacity(g.dtype);
+    int64_t Sm = 1;
+    int m = tile_axes(g, &Sm);
+    int walk = -1;
+    if (m >= 1 && m < g.d && fusion_level() >= 1 && o.walk != -2) {
+        if (o.walk >= 0 && walk_ok(g, m, Sm, o.walk)) {
+            walk = o.walk;
+        } else if (o.walk == -1) {
+            auto c = walk_candidates(g);
+            if (!c.empty()) walk = c.front();
+        }
+    }
+    if (walk >= 0) {
+        Step s;
+        s.kind = Step::TW;
+        for (int k = 0; k < m; ++k) s.axes.push_back(k);
+        s.axes.push_back(walk);
+        s.key = walk;
+        s.tw.data = g.data;
+        s.tw.Sm = static_cast<int32_t>(Sm);
+        s.tw.Sw = g.st[walk];
+        s.tw.mid = g.st[walk] / Sm;
+        s.tw.nwg = (g.N / (g.n[walk] * g.st[walk])) * s.tw.mid;
+        s.tw.L = g.L[walk];
+        s.tw.B = default_tw_B(g.L[walk]);
+        s.tw.ept = Sm <= kTWThreads ? 1 : (Sm <= 2 * kTWThreads ? 2 : 4);
+        s.tw.g = make_tile_geom(g, m);
+        steps.push_back(s);
+    } else if (m >= 1) {
         Step s;
         s.kind = Step::TILE;
-        s.axis_lo = 0;
-        s.axis_hi = m;
+        for (int k = 0; k < m; ++k) s.axes.push_back(k);
+        s.key = m - 1;
         s.tile.data = g.data;
         s.tile.total = g.N;
         s.tile.g = make_tile_geom(g, m);
         int64_t target = std::max<int64_t>(Sm, std::min<int64_t>(cap, 2048));
-        if (have_tuned && !tuned.empty() && tuned[0] > 0) target = std::min<int64_t>(cap, Sm * tuned[0]);
+        if (o.tile_mult > 0) target = std::min<int64_t>(cap, Sm * o.tile_mult);
         int64_t mult = std::max<int64_t>(1, target / Sm);
         if (m == g.d) mult = 1;  // the whole grid is one tile
         s.tile.chunk = static_cast<int32_t>(Sm * mult);
@@ -356,8 +465,8 @@ std::vector<Step> build_schedule(int op, const Geom &g) {
         for (int lev = 2; lev <= g.L[0]; ++lev) {
             Step s;
             s.kind = Step::LEVEL;
-            s.axis_lo = 0;
-            s.axis_hi = 1;
+            s.axes = {0};
+            s.key = 0;
             s.level.data = g.data;
             s.level.S = 1;
             s.level.outer = g.N / g.n[0];
@@ -368,32 +477,34 @@ std::vector<Step> build_schedule(int op, const Geom &g) {
         m = 1;
     }
     for (int k = m; k < g.d; ++k) {
+        if (k == walk) continue;
         const int L = g.L[k];
         int B = default_pole_B(L);
-        bool forced = false;
-        {
-            std::lock_guard<std::mutex> lk(g_override_mu);
-            forced = L <= SGH_MAX_LEVEL && g_pole_B_override[L] > 0;
+        int nt = 256;
+        const int code = static_cast<size_t>(k) < o.pole_code.size() ? o.pole_code[static_cast<size_t>(k)] : 0;
+        if (pole_B_override(L) == 0 && code > 0 && pole_supported(L, code / 1000)) {
+            B = code / 1000;
+            nt = code % 1000;
+            if (nt != 64 && nt != 128 && nt != 256) nt = 256;
         }
-        if (!forced && have_tuned && tuned.size() > static_cast<size_t>(k) && tuned[k] > 0 && pole_supported(L, tuned[k]))
-            B = tuned[k];
         if (L <= kPoleMaxLevel && pole_supported(L, B)) {
             Step s;
             s.kind = Step::POLE;
-            s.axis_lo = k;
-            s.axis_hi = k + 1;
+            s.axes = {k};
+            s.key = k;
             s.pole.data = g.data;
             s.pole.npoles = g.N / g.n[k];
             s.pole.S = g.st[k];
             s.pole.L = L;
             s.pole.B = B;
+            s.ptune.nt = nt;
             steps.push_back(s);
         } else {
             for (int lev = 2; lev <= L; ++lev) {
                 Step s;
                 s.kind = Step::LEVEL;
-                s.axis_lo = k;
-                s.axis_hi = k + 1;
+                s.axes = {k};
+                s.key = k;
                 s.level.data = g.data;
                 s.level.S = g.st[k];
                 s.level.outer = g.N / (g.n[k] * g.st[k]);
@@ -403,14 +514,10 @@ std::vector<Step> build_schedule(int op, const Geom &g) {
             }
         }
     }
-    // Inverse and transpose: the reverse sequence (per-level steps of one axis
-    // keep the order their operation needs: coarse to fine).
     if (op != SGH_OP_HIERARCHIZE) {
-        std::vector<Step> rev;
-        for (int k = g.d - 1; k >= 0; --k)
-            for (auto &s : steps)
-                if (s.axis_lo <= k && k < s.axis_hi && (s.axis_hi - 1 == k)) rev.push_back(s);
-        steps.swap(rev);
+        // Inverse and transpose: launches in reverse axis order; the per-level
+        // launches of one long pole keep their coarse-to-fine order.
+        std::stable_sort(steps.begin(), steps.end(), [](const Step &a, const Step &b) { return a.key > b.key; });
     } else {
         // hierarchization of a long pole runs its levels fine to coarse
         std::vector<Step> out;
@@ -421,7 +528,7 @@ std::vector<Step> build_schedule(int op, const Geom &g) {
                 continue;
             }
             size_t j = i;
-            while (j < steps.size() && steps[j].kind == Step::LEVEL && steps[j].axis_lo == steps[i].axis_lo) ++j;
+            while (j < steps.size() && steps[j].kind == Step::LEVEL && steps[j].key == steps[i].key) ++j;
             for (size_t t = j; t > i; --t) out.push_back(steps[t - 1]);
             i = j;
         }
@@ -430,11 +537,20 @@ std::vector<Step> build_schedule(int op, const Geom &g) {
     return steps;
 }
 
+// The schedule the library uses: autotuned choices when cached, else defaults.
+std::vector<Step> build_schedule(int op, const Geom &g) {
+    std::vector<int> tuned;
+    SchedOpts o;
+    if (tune_get(grid_key(op, g), &tuned)) o = opts_from_tuned(g, tuned);
+    return build_schedule_opts(op, g, o);
+}
+
 void retarget(std::vector<Step> &steps, void *data) {
     for (auto &s : steps) {
         s.tile.data = data;
         s.pole.data = data;
         s.level.data = data;
+        s.tw.data = data;
     }
 }
 
@@ -442,6 +558,7 @@ const char *step_name(const Step &s) {
     switch (s.kind) {
         case Step::TILE: return "tile";
         case Step::POLE: return "pole";
+        case Step::TW: return "tw";
         default: return "level";
     }
 }
@@ -452,6 +569,7 @@ std::string step_timer_name(int op, int dtype, const Step &s) {
     ss << ops[op] << "_" << (dtype == SGH_F64 ? "f64" : "f32") << "_" << step_name(s);
     if (s.kind == Step::POLE) ss << "_L" << s.pole.L;
     if (s.kind == Step::TILE) ss << "_m" << s.tile.g.m;
+    if (s.kind == Step::TW) ss << "_m" << s.tw.g.m << "_L" << s.tw.L;
     return ss.str();
 }
 
@@ -461,6 +579,7 @@ hipError_t run_step(int op, int dtype, const Step &s, hipStream_t st) {
     switch (s.kind) {
         case Step::TILE: return launch_tile(op, dtype, s.tile, s.ttune, st);
         case Step::POLE: return launch_pole(op, dtype, s.pole, s.ptune, st);
+        case Step::TW: return launch_tw(op, dtype, s.tw, st);
         default: return launch_level(op, dtype, s.level, st);
     }
 }
@@ -468,21 +587,24 @@ hipError_t run_step(int op, int dtype, const Step &s, hipStream_t st) {
 std::string describe_steps(int op, const Geom &g, const std::vector<Step> &steps) {
     std::ostringstream ss;
     ss << "{\"op\":" << op << ",\"dtype\":" << g.dtype << ",\"points\":" << g.N << ",\"launches\":[";
+    int trips = 0;
     for (size_t i = 0; i < steps.size(); ++i) {
         const Step &s = steps[i];
         if (i) ss << ",";
-        ss << "{\"kind\":\"" << step_name(s) << "\",\"axes\":[" << s.axis_lo << "," << s.axis_hi << "]";
+        ss << "{\"kind\":\"" << step_name(s) << "\",\"axes\":[";
+        for (size_t a = 0; a < s.axes.size(); ++a) ss << (a ? "," : "") << s.axes[a];
+        ss << "]";
         if (s.kind == Step::TILE)
             ss << ",\"chunk\":" << s.tile.chunk << ",\"nt\":" << s.ttune.nt << ",\"ept\":" << s.ttune.ept;
         if (s.kind == Step::POLE) ss << ",\"L\":" << s.pole.L << ",\"B\":" << s.pole.B << ",\"nt\":" << s.ptune.nt;
         if (s.kind == Step::LEVEL) ss << ",\"L\":" << s.level.L << ",\"lev\":" << s.level.lev;
+        if (s.kind == Step::TW)
+            ss << ",\"L\":" << s.tw.L << ",\"B\":" << s.tw.B << ",\"ept\":" << s.tw.ept << ",\"tile\":" << s.tw.Sm
+               << ",\"workgroups\":" << s.tw.nwg;
         ss << "}";
+        trips += (s.kind == Step::LEVEL) ? 0 : 1;
     }
-    ss << "],\"hbm_round_trips\":" << [&] {
-        int r = 0;
-        for (auto &s : steps) r += (s.kind == Step::LEVEL) ? 0 : 1;
-        return r;
-    }() << "}";
+    ss << "],\"hbm_round_trips\":" << trips << "}";
     return ss.str();
 }
 
@@ -721,7 +843,13 @@ int autotune_group(sgh_plan *p, BatchGroup &bg) {
 
 // Autotune the schedule of one large grid: tile chunk multiplier and pole
 // block spans, each timed alone on a scratch grid of the same shape.
+bool autotune_verbose() {
+    const char *v = std::getenv("SGH_AUTOTUNE_VERBOSE");
+    return v && *v && *v != '0';
+}
+
 int autotune_large(sgh_plan *p, PlanLarge &lg) {
+    const bool verbose = autotune_verbose();
     const std::string key = grid_key(p->op, lg.geom);
     std::vector<int> cached;
     if (tune_get(key, &cached)) {
@@ -735,50 +863,81 @@ int autotune_large(sgh_plan *p, PlanLarge &lg) {
     (void)hipMemset(scratch, 0, static_cast<size_t>(lg.geom.N) * es);
     hipStream_t st = nullptr;
     e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    std::vector<int> choice(static_cast<size_t>(lg.geom.d), 0);
+    SchedOpts best_opts;
+    float best_total = 1e30f;
     if (e == hipSuccess) {
         Geom sg = lg.geom;
         sg.data = scratch;
-        auto base = build_schedule(p->op, sg);
-        for (auto &s : base) {
-            if (s.kind == Step::TILE && s.tile.g.m < sg.d) {
-                int64_t Sm = 1;
-                for (int k = 0; k < s.tile.g.m; ++k) Sm *= sg.n[k];
-                float best = 1e30f;
-                int bestm = 0;
-                for (int mult : {1, 2, 4, 8, 16}) {
-                    if (Sm * mult > tile_capacity(sg.dtype)) break;
-                    Step c = s;
-                    c.tile.chunk = static_cast<int32_t>(Sm * mult);
-                    choose_tile_tune(c.tile.chunk, &c.ttune);
-                    const float ms = time_median([&](hipStream_t x) { return run_step(p->op, sg.dtype, c, x); }, st, 3);
-                    if (ms < best) {
-                        best = ms;
-                        bestm = mult;
+        std::vector<int> walks = walk_candidates(sg);
+        walks.push_back(-2);  // no fused walk
+        for (int walk : walks) {
+            SchedOpts o;
+            o.walk = walk;
+            o.pole_code.assign(static_cast<size_t>(sg.d), 0);
+            auto base = build_schedule_opts(p->op, sg, o);
+            for (auto &s : base) {
+                if (s.kind == Step::TILE && s.tile.g.m < sg.d) {
+                    int64_t Sm = 1;
+                    for (int k = 0; k < s.tile.g.m; ++k) Sm *= sg.n[k];
+                    float best = 1e30f;
+                    for (int mult : {1, 2, 4, 8, 16}) {
+                        if (Sm * mult > tile_capacity(sg.dtype)) break;
+                        Step c = s;
+                        c.tile.chunk = static_cast<int32_t>(Sm * mult);
+                        choose_tile_tune(c.tile.chunk, &c.ttune);
+                        const float ms =
+                            time_median([&](hipStream_t x) { return run_step(p->op, sg.dtype, c, x); }, st, 3);
+                        if (verbose)
+                            std::fprintf(stderr, "[sgh autotune] %s tile m=%d chunk=%d: %.4f ms\n", key.c_str(),
+                                         s.tile.g.m, c.tile.chunk, ms);
+                        if (ms < best) {
+                            best = ms;
+                            o.tile_mult = mult;
+                        }
+                    }
+                } else if (s.kind == Step::POLE && pole_B_override(s.pole.L) == 0) {
+                    float best = 1e30f;
+                    for (int B = 2; B <= s.pole.L; ++B) {
+                        if (!pole_supported(s.pole.L, B)) continue;
+                        for (int nt : {64, 128, 256}) {
+                            Step c = s;
+                            c.pole.B = B;
+                            c.ptune.nt = nt;
+                            const float ms =
+                                time_median([&](hipStream_t x) { return run_step(p->op, sg.dtype, c, x); }, st, 3);
+                            if (verbose)
+                                std::fprintf(stderr, "[sgh autotune] %s axis %d pole L=%d B=%d nt=%d: %.4f ms\n",
+                                             key.c_str(), s.key, s.pole.L, B, nt, ms);
+                            if (ms < best) {
+                                best = ms;
+                                o.pole_code[static_cast<size_t>(s.key)] = B * 1000 + nt;
+                            }
+                        }
                     }
                 }
-                choice[0] = bestm;
-            } else if (s.kind == Step::POLE) {
-                float best = 1e30f;
-                int bestB = s.pole.B;
-                for (int B = 2; B <= s.pole.L; ++B) {
-                    if (!pole_supported(s.pole.L, B)) continue;
-                    Step c = s;
-                    c.pole.B = B;
-                    const float ms = time_median([&](hipStream_t x) { return run_step(p->op, sg.dtype, c, x); }, st, 3);
-                    if (ms < best) {
-                        best = ms;
-                        bestB = B;
+            }
+            auto steps = build_schedule_opts(p->op, sg, o);
+            const float total = time_median(
+                [&](hipStream_t x) {
+                    for (auto &s : steps) {
+                        hipError_t r = run_step(p->op, sg.dtype, s, x);
+                        if (r != hipSuccess) return r;
                     }
-                }
-                choice[static_cast<size_t>(s.axis_lo)] = bestB;
+                    return hipSuccess;
+                },
+                st, 5);
+            if (verbose)
+                std::fprintf(stderr, "[sgh autotune] %s walk=%d schedule: %.4f ms\n", key.c_str(), walk, total);
+            if (total < best_total) {
+                best_total = total;
+                best_opts = o;
             }
         }
     }
     if (st) (void)hipStreamDestroy(st);
     (void)hipFree(scratch);
     if (e != hipSuccess) return hip_fail(e, "autotune");
-    tune_put(key, choice);
+    tune_put(key, tuned_from_opts(lg.geom, best_opts));
     lg.steps = build_schedule(p->op, lg.geom);
     return SGH_OK;
 }
@@ -1017,6 +1176,14 @@ int sgh_set_pole_block(int32_t level, int32_t block_exponent) {
         return fail(SGH_ERR_UNSUPPORTED, "no pole kernel for level %d with block exponent %d", level, block_exponent);
     std::lock_guard<std::mutex> lk(g_override_mu);
     g_pole_B_override[level] = block_exponent;
+    return SGH_OK;
+}
+
+int sgh_set_fusion(int32_t level) {
+    using namespace sgh;
+    if (level < 0 || level > 1) return fail(SGH_ERR_ARG, "fusion level %d outside 0..1", level);
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    g_fusion = level;
     return SGH_OK;
 }
 

@@ -54,6 +54,22 @@ struct PoleLaunch {
     int32_t B;
 };
 
+// Leading tile axes fused with one walked strided axis: workgroup w owns the
+// pencil of all tile elements over the whole walked pole, at element offset
+// (w / mid) * n * Sw + (w % mid) * Sm; row p (1-based position on the walked
+// axis) starts (p - 1) * Sw elements further.
+struct TWLaunch {
+    void *data;
+    int64_t nwg;  // pencils: (N / (n * Sw)) * mid
+    int64_t mid;  // Sw / Sm
+    int64_t Sw;   // stride of the walked axis (elements)
+    int32_t Sm;   // tile size (elements of one row)
+    int32_t L;    // level of the walked axis
+    int32_t B;    // block exponent along the walked axis
+    int32_t ept;  // tile elements per thread (threads = 1024)
+    TileGeom g;   // tile axes
+};
+
 // One level of the generic per-level fallback for long poles.
 struct LevelLaunch {
     void *data;
@@ -86,6 +102,7 @@ struct BatchTune {
     hipError_t launch_tile_##SUF(const TileLaunch &p, const TileTune &t, hipStream_t s);              \
     hipError_t launch_pole_##SUF(const PoleLaunch &p, const PoleTune &t, hipStream_t s);              \
     hipError_t launch_level_##SUF(const LevelLaunch &p, hipStream_t s);                              \
+    hipError_t launch_tw_##SUF(const TWLaunch &p, hipStream_t s);                                     \
     hipError_t launch_batch_##SUF(const BatchTask *dev_tasks, int32_t ntasks, uint32_t *dev_counters, \
                                   const BatchTune &t, hipStream_t s);
 SGH_DECLARE_LAUNCHERS(f64_h)
@@ -119,6 +136,7 @@ inline hipError_t launch_pole(int op, int dtype, const PoleLaunch &p, const Pole
 inline hipError_t launch_level(int op, int dtype, const LevelLaunch &p, hipStream_t s) {
     SGH_ROUTE(launch_level, p, s);
 }
+inline hipError_t launch_tw(int op, int dtype, const TWLaunch &p, hipStream_t s) { SGH_ROUTE(launch_tw, p, s); }
 inline hipError_t launch_batch(int op, int dtype, const BatchTask *dev_tasks, int32_t ntasks,
                                uint32_t *dev_counters, const BatchTune &t, hipStream_t s) {
     SGH_ROUTE(launch_batch, dev_tasks, ntasks, dev_counters, t, s);
@@ -126,6 +144,12 @@ inline hipError_t launch_batch(int op, int dtype, const BatchTask *dev_tasks, in
 #undef SGH_ROUTE
 
 bool pole_supported(int L, int B);
+// Threads per workgroup of the fused tile + walked-axis kernel, and the
+// (L, B, ept) combinations it is built for.
+constexpr int kTWThreads = 1024;
+bool tw_supported(int L, int B, int ept);
+// LDS rows staged at once by the fused kernel: 16 / ept rows of the tile.
+constexpr int tw_rows_per_batch(int ept) { return 16 / ept; }
 bool tile_ept_supported(int ept);
 bool batch_ept_supported(int ept);
 int max_lds_bytes();

@@ -76,6 +76,7 @@ def lib():
             "sgh_version": ([], ctypes.c_char_p),
             "sgh_timing_enable": ([i32], ctypes.c_int),
             "sgh_set_pole_block": ([i32, i32], ctypes.c_int),
+            "sgh_set_fusion": ([i32], ctypes.c_int),
             "sgh_timing_reset": ([], ctypes.c_int),
             "sgh_timing_report": ([ctypes.c_char_p, i32], ctypes.c_int),
         }
@@ -256,6 +257,11 @@ def schedule(op: int, levels, dtype: int = F64) -> dict:
 def set_pole_block(level: int, block_exponent: int):
     """Force the register block span 2**block_exponent for strided poles of `level` (0 = default)."""
     _check(lib().sgh_set_pole_block(int(level), int(block_exponent)), "sgh_set_pole_block")
+
+
+def set_fusion(level: int):
+    """1 (default): fuse the LDS-tile axes with one register-walked strided axis; 0: one launch per pass."""
+    _check(lib().sgh_set_fusion(int(level)), "sgh_set_fusion")
 
 
 # POLE_PAIRS: (level, block exponent) pairs of the register-resident pole kernel

@@ -94,15 +94,18 @@ def test_num_points():
 def test_schedules():
     s = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D)
     kinds = [(l["kind"], tuple(l["axes"])) for l in s["launches"]]
-    assert kinds == [("tile", (0, 1)), ("pole", (1, 2)), ("pole", (2, 3))]
-    assert [l.get("L") for l in s["launches"][1:]] == [9, 8]
+    # axis 0 in an LDS tile fused with axis 2 walked in registers; axis 1 strided
+    assert kinds == [("tw", (0, 2)), ("pole", (1,))]
+    assert [l.get("L") for l in s["launches"]] == [8, 9]
+    assert s["hbm_round_trips"] == 2
     d = sgh.schedule(sgh.OP_DEHIERARCHIZE, W.ANISO_3D)
-    assert [tuple(l["axes"]) for l in d["launches"]] == [(2, 3), (1, 2), (0, 1)]
+    assert [tuple(l["axes"]) for l in d["launches"]] == [(0, 2), (1,)]
     s5 = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_5D)
     assert [(l["kind"], tuple(l["axes"])) for l in s5["launches"]] == [
-        ("tile", (0, 2)), ("pole", (2, 3)), ("pole", (3, 4)), ("pole", (4, 5))]
+        ("tw", (0, 1, 4)), ("pole", (2,)), ("pole", (3,))]
+    assert s5["launches"][0]["ept"] == 4 and s5["launches"][0]["tile"] == 63 * 63
     small = sgh.schedule(sgh.OP_HIERARCHIZE, W.SMALL_2D)
-    assert [(l["kind"], tuple(l["axes"])) for l in small["launches"]] == [("tile", (0, 2))]
+    assert [(l["kind"], tuple(l["axes"])) for l in small["launches"]] == [("tile", (0, 1))]
     # level-1 axes are the identity and are dropped
     assert sgh.schedule(sgh.OP_HIERARCHIZE, (1, 1))["launches"] == []
     # long poles use the per-level fallback: contiguous l=14 needs 13 levels
@@ -112,3 +115,23 @@ def test_schedules():
     lv = sgh.schedule(sgh.OP_ADJOINT, (3, 12))["launches"]
     assert lv[0]["kind"] == "level" and [l["lev"] for l in lv[:11]] == list(range(2, 13))
     assert lv[-1]["kind"] == "tile"
+    # a walked axis that is not the last one (the last is too long for registers)
+    lv = sgh.schedule(sgh.OP_HIERARCHIZE, (10, 4, 9))["launches"]
+    assert [(l["kind"], tuple(l["axes"])) for l in lv] == [("tw", (0, 1)), ("pole", (2,))]
+
+
+def test_fusion_switch():
+    try:
+        sgh.set_fusion(0)
+        s = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D)
+        assert [(l["kind"], tuple(l["axes"])) for l in s["launches"]] == [
+            ("tile", (0,)), ("pole", (1,)), ("pole", (2,))]
+        d = sgh.schedule(sgh.OP_ADJOINT, W.ANISO_3D)
+        assert [tuple(l["axes"]) for l in d["launches"]] == [(2,), (1,), (0,)]
+    finally:
+        sgh.set_fusion(1)
+    with pytest.raises(sgh.SghError):
+        sgh.set_fusion(5)
+    assert sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D)["launches"][0]["kind"] == "tw"
+    with pytest.raises(sgh.SghError):
+        sgh.set_pole_block(9, 7)

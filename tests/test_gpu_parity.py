@@ -53,6 +53,7 @@ def test_every_pole_block_split(L, B, dtype):
     """Every (level, block) variant of the register-resident strided kernel, at a
     stride large enough for full coalescing and at a tiny stride (ragged rows)."""
     sgh.set_pole_block(L, B)
+    sgh.set_fusion(0)  # keep the strided axis in the pole kernel
     cap = 8192 if dtype == np.float64 else 16384  # points of the leading-axes LDS tile
     leads = [(12,) if dtype == np.float64 else (13,)]  # wide stride: 4095 / 8191 lanes per row
     if 31 * ((1 << L) - 1) > cap:
@@ -74,15 +75,68 @@ def test_every_pole_block_split(L, B, dtype):
                 assert err <= TOL[dtype], (OP_NAME[op], err)
     finally:
         sgh.set_pole_block(L, 0)
+        sgh.set_fusion(1)
 
 
 def test_fp64_matches_oracle_bitwise_on_pole_and_tile_paths():
-    """Same update order as the oracle, and 0.5*a is exact: FP64 results agree bit for bit."""
-    for levels in [(7, 7), (10, 4, 3), (5, 9), (3, 11)]:
-        x = W.uniform(levels, 5)
-        for op in OPS:
-            got = gpu_run(op, x, levels)
-            assert np.array_equal(got, ORACLE[op](x, levels)), (levels, OP_NAME[op])
+    """Same update order as the oracle, and 0.5*a is exact: FP64 results agree bit for bit
+    when every axis has its own launch (the fused launch reorders axes, which only rounds
+    differently)."""
+    sgh.set_fusion(0)
+    try:
+        for levels in [(7, 7), (10, 4, 3), (5, 9), (3, 11)]:
+            x = W.uniform(levels, 5)
+            for op in OPS:
+                got = gpu_run(op, x, levels)
+                assert np.array_equal(got, ORACLE[op](x, levels)), (levels, OP_NAME[op])
+    finally:
+        sgh.set_fusion(1)
+
+
+def _tw_shape(ept, L, dtype):
+    """A grid whose schedule fuses a leading tile of 1023 / 2047 / 4095 points with a
+    walked strided axis of level L (the middle axis keeps the grid out of one tile)."""
+    lead = {1: 10, 2: 11, 4: 12}[ept]
+    cap = 8192 if dtype == np.float64 else 16384
+    mid = 2
+    while ((1 << lead) - 1) * ((1 << mid) - 1) <= cap:
+        mid += 1
+    return (lead, mid, L)
+
+
+TW_COMBOS = [(2, 1), (3, 1), (4, 1), (5, 1), (6, 1), (7, 1), (8, 1), (2, 2), (3, 2), (4, 2), (5, 2), (6, 2),
+             (2, 4), (3, 4), (4, 4), (5, 4)]
+
+
+@pytest.mark.parametrize("L,ept", TW_COMBOS)
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_fused_tile_walk(L, ept, dtype):
+    levels = _tw_shape(ept, L, dtype)
+    sched = sgh.schedule(sgh.OP_HIERARCHIZE, levels, sgh.F64 if dtype == np.float64 else sgh.F32)
+    tw = [l for l in sched["launches"] if l["kind"] == "tw"]
+    assert len(tw) == 1 and tw[0]["axes"] == [0, 2] and tw[0]["ept"] == ept and tw[0]["L"] == L, sched
+    x = W.uniform(levels, [23, L, ept], dtype)
+    x64 = x.astype(np.float64)
+    for op in OPS:
+        ref = ORACLE[op](x64, levels)
+        got = gpu_run(op, x, levels)
+        err = rel_err(op, x64, got, ref)
+        print("tw levels=%s ept=%d op=%s err=%.3e" % (levels, ept, OP_NAME[op], err), flush=True)
+        assert err <= TOL[dtype], (OP_NAME[op], err)
+
+
+@pytest.mark.parametrize("levels", [(6, 6, 3, 5), (3, 4, 5, 5), (10, 4, 9), (10, 4, 3, 2), (5, 3, 2, 6, 2)], ids=ids)
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_fused_tile_walk_layouts(levels, dtype):
+    """Multi-axis tiles, a walked axis that is not the last one, and axes after it."""
+    sched = sgh.schedule(sgh.OP_HIERARCHIZE, levels, sgh.F64 if dtype == np.float64 else sgh.F32)
+    print(levels, [(l["kind"], l["axes"]) for l in sched["launches"]], flush=True)
+    x = W.uniform(levels, [24, len(levels)], dtype)
+    x64 = x.astype(np.float64)
+    for op in OPS:
+        ref = ORACLE[op](x64, levels)
+        got = gpu_run(op, x, levels)
+        assert rel_err(op, x64, got, ref) <= TOL[dtype], OP_NAME[op]
 
 
 def test_deterministic_and_in_place_safe():
