@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default schedule instead of autotuning it first")
     ap.add_argument("--copy-only", action="store_true",
                     help="only copy a buffer of the workload's size (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -120,6 +122,15 @@ def main():
     torch.cuda.synchronize()
     gen_s = time.time() - t0
 
+    tuned = {}
+    if not args.no_autotune:
+        # time the candidate schedules on scratch grids of the same shape; the
+        # one-shot calls below then use the chosen schedule (kept in-process)
+        for op in (sgh.OP_HIERARCHIZE, sgh.OP_DEHIERARCHIZE, sgh.OP_ADJOINT):
+            plan = sgh.Plan(op, [x], [levels], graph=False, autotune=True)
+            tuned[op] = plan.describe()["large"][0]["launches"]
+            plan.close()
+
     step = lambda: sgh.hierarchize(x, levels)
     for _ in range(args.warmup):
         step()
@@ -165,6 +176,8 @@ def main():
         "hbm_GBps_one_round_trip": whole_GBps,
         "hbm_frac_of_peak_one_round_trip": whole_GBps / HBM_PEAK_GBS,
         "launches_per_step": launches_per_step,
+        "schedule": tuned.get(sgh.OP_HIERARCHIZE) or sgh.schedule(sgh.OP_HIERARCHIZE, levels,
+                                                                   sgh.F64 if esize == 8 else sgh.F32)["launches"],
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

@@ -150,12 +150,20 @@ const char *sgh_version(void);
  * choice.  Returns SGH_ERR_UNSUPPORTED for pairs this build has no kernel for. */
 int sgh_set_pole_block(int32_t level, int32_t block_exponent);
 
+/* Tuning knob: poles of level `level` on strided axes use the three-level
+ * register walk: 2^top_exponent super-blocks of 2^block_exponent blocks of
+ * span 2^block_exponent (level = top_exponent + 2 * block_exponent), with the
+ * next group of rows prefetched when `prefetch` is 1.  block_exponent 0
+ * removes the override.  Returns SGH_ERR_UNSUPPORTED for splits this build has
+ * no kernel for. */
+int sgh_set_pole_split(int32_t level, int32_t top_exponent, int32_t block_exponent, int32_t prefetch);
+
 /* Schedule switch: level 1 (default) fuses the leading LDS-tile axes with one
  * strided axis walked in registers into a single launch (one HBM round trip
- * for both); level 0 keeps one launch for the tile axes and one per strided
- * axis.  Axes commute (Algorithm 1's outer loop may take the dimensions in any
- * order), so both give the same map.  Applies to schedules and plans built
- * after the call. */
+ * for both); level 2 does the same but keeps the walk two-level; level 0 keeps
+ * one launch for the tile axes and one per strided axis.  Axes commute
+ * (Algorithm 1's outer loop may take the dimensions in any order), so all give
+ * the same map.  Applies to schedules and plans built after the call. */
 int sgh_set_fusion(int32_t level);
 
 /* ---- measurement support ------------------------------------------------

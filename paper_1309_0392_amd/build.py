@@ -29,24 +29,27 @@ UNITS = [("sgh_kernels_%s_%s.hip" % (t, o), ["-x", "hip"] + DEVICE) for t in ("f
 UNITS.append(("sgh_api.cpp", ["-x", "hip"] + DEVICE))
 
 
-def _compile(src: str, flags) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + COMMON + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
-    subprocess.run(cmd, check=True)
-    return obj
+def build(verbose: bool = True, out: str = LIB, defines=(), build_dir: str = BUILD) -> str:
+    """Compile every unit and link the library (always rebuilds).  `defines` are
+    extra -D flags for tuning variants built elsewhere than the default path."""
+    os.makedirs(build_dir, exist_ok=True)
+    extra = ["-D" + d for d in defines]
 
+    def one(u):
+        src, flags = u
+        obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+        subprocess.run([HIPCC] + COMMON + extra + flags + ["-c", os.path.join(CSRC, src), "-o", obj], check=True)
+        return obj
 
-def build(verbose: bool = True) -> str:
-    """Compile every unit and link libsgh.so (always rebuilds)."""
-    os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(len(UNITS), max(1, os.cpu_count() or 1))) as ex:
-        objs = list(ex.map(lambda u: _compile(*u), UNITS))
-    tmp = LIB + ".tmp%d" % os.getpid()
+        objs = list(ex.map(one, UNITS))
+    LIB_OUT = out
+    tmp = LIB_OUT + ".tmp%d" % os.getpid()
     subprocess.run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, LIB_OUT)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", LIB_OUT)
+    return LIB_OUT
 
 
 if __name__ == "__main__":

@@ -283,11 +283,17 @@ struct Step {
 // sgh_set_pole_block, and the fusion switch set through sgh_set_fusion.
 std::mutex g_override_mu;
 int g_pole_B_override[SGH_MAX_LEVEL + 1] = {};
+int g_pole3_override[SGH_MAX_LEVEL + 1] = {};  // 1 + TB * 100 + B * 10 + pf, 0 = none
 int g_fusion = 1;
 
 int pole_B_override(int L) {
     std::lock_guard<std::mutex> lk(g_override_mu);
     return (L >= 0 && L <= SGH_MAX_LEVEL) ? g_pole_B_override[L] : 0;
+}
+
+int pole3_override(int L) {
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    return (L >= 0 && L <= SGH_MAX_LEVEL) ? g_pole3_override[L] : 0;
 }
 
 int fusion_level() {
@@ -352,12 +358,29 @@ std::string grid_key(int op, const Geom &g) {
 // pole_code[k]: B * 1000 + workgroup size for strided axis k (0 = default).
 struct SchedOpts {
     int walk = -1;
+    bool walk_two_level = false;  // force the two-level walk in the fused kernel
     int tile_mult = 0;
     std::vector<int> pole_code;
 };
 
+// Pole codes: two-level  B * 1000 + nt;  three-level  1000000 + TB * 100000 +
+// pf * 10000 + B * 1000 + nt.
+int pole_code2(int B, int nt) { return B * 1000 + nt; }
+int pole_code3(int TB, int B, int pf, int nt) { return 1000000 + TB * 100000 + pf * 10000 + B * 1000 + nt; }
+
+// Default three-level split of a strided pole (0 = keep the two-level walk).
+bool default_pole3(int L, int *TB, int *B) {
+    switch (L) {
+        case 8: *TB = 2; *B = 3; return true;
+        case 9: *TB = 3; *B = 3; return true;
+        case 10: *TB = 2; *B = 4; return true;
+        default: return false;
+    }
+}
+
 // Tuning-cache layout per grid: [tile_mult, pole_code_1 .. pole_code_{d-1}, walk code]
-// with walk code 0 = default, 1 = none, 2 + k = axis k.
+// with walk code 0 = default, 1 = none, 2 + k = axis k, 100 + k = axis k with
+// the two-level walk.
 SchedOpts opts_from_tuned(const Geom &g, const std::vector<int> &t) {
     SchedOpts o;
     o.pole_code.assign(static_cast<size_t>(g.d), 0);
@@ -365,7 +388,12 @@ SchedOpts opts_from_tuned(const Geom &g, const std::vector<int> &t) {
     for (int k = 1; k < g.d && static_cast<size_t>(k) < t.size(); ++k) o.pole_code[static_cast<size_t>(k)] = t[static_cast<size_t>(k)];
     if (t.size() > static_cast<size_t>(g.d)) {
         const int w = t[static_cast<size_t>(g.d)];
-        o.walk = w == 0 ? -1 : (w == 1 ? -2 : w - 2);
+        if (w >= 100) {
+            o.walk = w - 100;
+            o.walk_two_level = true;
+        } else {
+            o.walk = w == 0 ? -1 : (w == 1 ? -2 : w - 2);
+        }
     }
     return o;
 }
@@ -375,7 +403,8 @@ std::vector<int> tuned_from_opts(const Geom &g, const SchedOpts &o) {
     t[0] = o.tile_mult;
     for (int k = 1; k < g.d; ++k)
         t[static_cast<size_t>(k)] = static_cast<size_t>(k) < o.pole_code.size() ? o.pole_code[static_cast<size_t>(k)] : 0;
-    t[static_cast<size_t>(g.d)] = o.walk == -1 ? 0 : (o.walk == -2 ? 1 : o.walk + 2);
+    t[static_cast<size_t>(g.d)] =
+        o.walk == -1 ? 0 : (o.walk == -2 ? 1 : (o.walk_two_level ? 100 + o.walk : o.walk + 2));
     return t;
 }
 
@@ -397,7 +426,8 @@ bool walk_ok(const Geom &g, int m, int64_t Sm, int w) {
     if (m < 1 || w < m || w >= g.d || Sm > 4 * kTWThreads) return false;
     const int L = g.L[w];
     const int ept = Sm <= kTWThreads ? 1 : (Sm <= 2 * kTWThreads ? 2 : 4);
-    if (!tw_supported(L, default_tw_B(L), ept)) return false;
+    const bool three = ept == 1 && tw3_supported(L, L - 6, 3) && fusion_level() != 2;
+    if (!tw_supported(L, default_tw_B(L), ept) && !three) return false;
     // the pencil's byte offsets must fit the 32-bit buffer window
     const int64_t bytes = g.n[w] * g.st[w] * static_cast<int64_t>(esize_of(g.dtype));
     return bytes < (int64_t(1) << 32) - 1;
@@ -443,6 +473,13 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
         s.tw.L = g.L[walk];
         s.tw.B = default_tw_B(g.L[walk]);
         s.tw.ept = Sm <= kTWThreads ? 1 : (Sm <= 2 * kTWThreads ? 2 : 4);
+        const bool two_ok = tw_supported(s.tw.L, s.tw.B, s.tw.ept);
+        const bool three_ok = s.tw.ept == 1 && tw3_supported(s.tw.L, s.tw.L - 6, 3) && fusion_level() != 2;
+        if (three_ok && !(o.walk_two_level && two_ok)) {
+            s.tw.split = 3;
+            s.tw.TB = s.tw.L - 6;
+            s.tw.B = 3;
+        }
         s.tw.g = make_tile_geom(g, m);
         steps.push_back(s);
     } else if (m >= 1) {
@@ -481,13 +518,41 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
         const int L = g.L[k];
         int B = default_pole_B(L);
         int nt = 256;
+        int split = 2, TB = 0, pf = 0;
+        const int o3 = pole3_override(L);
+        if (o3 > 0) {
+            split = 3;
+            TB = (o3 - 1) / 100;
+            B = ((o3 - 1) / 10) % 10;
+            pf = (o3 - 1) % 10;
+        } else if (pole_B_override(L) == 0) {
+            int tb3 = 0, b3 = 0;
+            if (default_pole3(L, &tb3, &b3)) {
+                split = 3;
+                TB = tb3;
+                B = b3;
+            }
+        }
         const int code = static_cast<size_t>(k) < o.pole_code.size() ? o.pole_code[static_cast<size_t>(k)] : 0;
-        if (pole_B_override(L) == 0 && code > 0 && pole_supported(L, code / 1000)) {
+        if (o3 > 0) {
+            // forced split; ignore the tuned choice
+        } else if (pole_B_override(L) == 0 && code >= 1000000) {
+            const int c = code - 1000000;
+            const int tb = c / 100000, cpf = (c / 10000) % 10, cb = (c / 1000) % 10, cnt = c % 1000;
+            if (pole3_supported(L, tb, cb) && cnt == 256) {
+                split = 3;
+                TB = tb;
+                B = cb;
+                pf = cpf;
+                nt = cnt;
+            }
+        } else if (pole_B_override(L) == 0 && code > 0 && pole_supported(L, code / 1000)) {
+            split = 2;
             B = code / 1000;
             nt = code % 1000;
-            if (nt != 64 && nt != 128 && nt != 256) nt = 256;
+            if (nt != 64 && nt != 128 && nt != 256 && nt != 512) nt = 256;
         }
-        if (L <= kPoleMaxLevel && pole_supported(L, B)) {
+        if (L <= kPoleMaxLevel && (split == 3 ? pole3_supported(L, TB, B) : pole_supported(L, B))) {
             Step s;
             s.kind = Step::POLE;
             s.axes = {k};
@@ -497,6 +562,9 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
             s.pole.S = g.st[k];
             s.pole.L = L;
             s.pole.B = B;
+            s.pole.split = split;
+            s.pole.TB = TB;
+            s.pole.pf = pf;
             s.ptune.nt = nt;
             steps.push_back(s);
         } else {
@@ -596,11 +664,13 @@ std::string describe_steps(int op, const Geom &g, const std::vector<Step> &steps
         ss << "]";
         if (s.kind == Step::TILE)
             ss << ",\"chunk\":" << s.tile.chunk << ",\"nt\":" << s.ttune.nt << ",\"ept\":" << s.ttune.ept;
-        if (s.kind == Step::POLE) ss << ",\"L\":" << s.pole.L << ",\"B\":" << s.pole.B << ",\"nt\":" << s.ptune.nt;
+        if (s.kind == Step::POLE)
+            ss << ",\"L\":" << s.pole.L << ",\"B\":" << s.pole.B << ",\"split\":" << s.pole.split << ",\"TB\":" << s.pole.TB
+               << ",\"prefetch\":" << s.pole.pf << ",\"nt\":" << s.ptune.nt;
         if (s.kind == Step::LEVEL) ss << ",\"L\":" << s.level.L << ",\"lev\":" << s.level.lev;
         if (s.kind == Step::TW)
-            ss << ",\"L\":" << s.tw.L << ",\"B\":" << s.tw.B << ",\"ept\":" << s.tw.ept << ",\"tile\":" << s.tw.Sm
-               << ",\"workgroups\":" << s.tw.nwg;
+            ss << ",\"L\":" << s.tw.L << ",\"B\":" << s.tw.B << ",\"split\":" << s.tw.split << ",\"TB\":" << s.tw.TB
+               << ",\"ept\":" << s.tw.ept << ",\"tile\":" << s.tw.Sm << ",\"workgroups\":" << s.tw.nwg;
         ss << "}";
         trips += (s.kind == Step::LEVEL) ? 0 : 1;
     }
@@ -868,11 +938,26 @@ int autotune_large(sgh_plan *p, PlanLarge &lg) {
     if (e == hipSuccess) {
         Geom sg = lg.geom;
         sg.data = scratch;
-        std::vector<int> walks = walk_candidates(sg);
-        walks.push_back(-2);  // no fused walk
-        for (int walk : walks) {
+        std::vector<std::pair<int, bool>> walks;
+        for (int w : walk_candidates(sg)) {
+            walks.push_back({w, false});
+            walks.push_back({w, true});  // two-level walk, where both exist
+        }
+        walks.push_back({-2, false});  // no fused walk
+        for (auto wv : walks) {
+            const int walk = wv.first;
             SchedOpts o;
             o.walk = walk;
+            o.walk_two_level = wv.second;
+            if (wv.second) {
+                int64_t Sm = 1;
+                const int m = tile_axes(sg, &Sm);
+                const int L = sg.L[walk];
+                const int ept = Sm <= kTWThreads ? 1 : (Sm <= 2 * kTWThreads ? 2 : 4);
+                (void)m;
+                // the two-level trial only differs where the three-level walk is the default
+                if (!(ept == 1 && tw3_supported(L, L - 6, 3)) || !tw_supported(L, default_tw_B(L), ept)) continue;
+            }
             o.pole_code.assign(static_cast<size_t>(sg.d), 0);
             auto base = build_schedule_opts(p->op, sg, o);
             for (auto &s : base) {
@@ -895,25 +980,45 @@ int autotune_large(sgh_plan *p, PlanLarge &lg) {
                             o.tile_mult = mult;
                         }
                     }
-                } else if (s.kind == Step::POLE && pole_B_override(s.pole.L) == 0) {
+                } else if (s.kind == Step::POLE && pole_B_override(s.pole.L) == 0 && pole3_override(s.pole.L) == 0) {
                     float best = 1e30f;
+                    auto trial = [&](Step c, int code, const char *what) {
+                        const float ms =
+                            time_median([&](hipStream_t x) { return run_step(p->op, sg.dtype, c, x); }, st, 3);
+                        if (verbose)
+                            std::fprintf(stderr, "[sgh autotune] %s axis %d pole L=%d %s B=%d TB=%d pf=%d nt=%d: %.4f ms\n",
+                                         key.c_str(), s.key, s.pole.L, what, c.pole.B, c.pole.TB, c.pole.pf,
+                                         c.ptune.nt, ms);
+                        if (ms < best) {
+                            best = ms;
+                            o.pole_code[static_cast<size_t>(s.key)] = code;
+                        }
+                    };
                     for (int B = 2; B <= s.pole.L; ++B) {
                         if (!pole_supported(s.pole.L, B)) continue;
-                        for (int nt : {64, 128, 256}) {
+                        for (int nt : {128, 256, 512}) {
                             Step c = s;
+                            c.pole.split = 2;
+                            c.pole.TB = 0;
+                            c.pole.pf = 0;
                             c.pole.B = B;
                             c.ptune.nt = nt;
-                            const float ms =
-                                time_median([&](hipStream_t x) { return run_step(p->op, sg.dtype, c, x); }, st, 3);
-                            if (verbose)
-                                std::fprintf(stderr, "[sgh autotune] %s axis %d pole L=%d B=%d nt=%d: %.4f ms\n",
-                                             key.c_str(), s.key, s.pole.L, B, nt, ms);
-                            if (ms < best) {
-                                best = ms;
-                                o.pole_code[static_cast<size_t>(s.key)] = B * 1000 + nt;
-                            }
+                            trial(c, pole_code2(B, nt), "2-level");
                         }
                     }
+                    for (int TB = 0; TB <= 6; ++TB)
+                        for (int B = 2; B <= 5; ++B) {
+                            if (!pole3_supported(s.pole.L, TB, B)) continue;
+                            for (int pf = 0; pf <= 1; ++pf) {
+                                Step c = s;
+                                c.pole.split = 3;
+                                c.pole.TB = TB;
+                                c.pole.B = B;
+                                c.pole.pf = pf;
+                                c.ptune.nt = 256;
+                                trial(c, pole_code3(TB, B, pf, 256), "3-level");
+                            }
+                        }
                 }
             }
             auto steps = build_schedule_opts(p->op, sg, o);
@@ -927,7 +1032,8 @@ int autotune_large(sgh_plan *p, PlanLarge &lg) {
                 },
                 st, 5);
             if (verbose)
-                std::fprintf(stderr, "[sgh autotune] %s walk=%d schedule: %.4f ms\n", key.c_str(), walk, total);
+                std::fprintf(stderr, "[sgh autotune] %s walk=%d%s schedule: %.4f ms\n", key.c_str(), walk,
+                             wv.second ? " (2-level)" : "", total);
             if (total < best_total) {
                 best_total = total;
                 best_opts = o;
@@ -1179,9 +1285,25 @@ int sgh_set_pole_block(int32_t level, int32_t block_exponent) {
     return SGH_OK;
 }
 
+int sgh_set_pole_split(int32_t level, int32_t top_exponent, int32_t block_exponent, int32_t prefetch) {
+    using namespace sgh;
+    if (level < 2 || level > SGH_MAX_LEVEL) return fail(SGH_ERR_ARG, "level %d outside 2..%d", level, SGH_MAX_LEVEL);
+    if (block_exponent == 0) {
+        std::lock_guard<std::mutex> lk(g_override_mu);
+        g_pole3_override[level] = 0;
+        return SGH_OK;
+    }
+    if (!pole3_supported(level, top_exponent, block_exponent) || prefetch < 0 || prefetch > 1)
+        return fail(SGH_ERR_UNSUPPORTED, "no three-level pole kernel for level %d = %d + 2*%d", level, top_exponent,
+                    block_exponent);
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    g_pole3_override[level] = 1 + top_exponent * 100 + block_exponent * 10 + prefetch;
+    return SGH_OK;
+}
+
 int sgh_set_fusion(int32_t level) {
     using namespace sgh;
-    if (level < 0 || level > 1) return fail(SGH_ERR_ARG, "fusion level %d outside 0..1", level);
+    if (level < 0 || level > 2) return fail(SGH_ERR_ARG, "fusion level %d outside 0..2", level);
     std::lock_guard<std::mutex> lk(g_override_mu);
     g_fusion = level;
     return SGH_OK;

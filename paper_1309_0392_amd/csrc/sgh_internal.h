@@ -46,12 +46,18 @@ struct BatchTask {
 };
 
 // Strided axis: npoles = outer * S poles of n = 2^L - 1 points at stride S.
+// split 2: blocks of span 2^B between coarse points (2^(L-B) blocks);
+// split 3: 2^TB super-blocks of 2^B blocks of span 2^B (L = TB + 2B), with the
+// next group of rows prefetched when pf is set.
 struct PoleLaunch {
     void *data;
     int64_t npoles;
     int64_t S;
     int32_t L;
     int32_t B;
+    int32_t split = 2;
+    int32_t TB = 0;
+    int32_t pf = 0;
 };
 
 // Leading tile axes fused with one walked strided axis: workgroup w owns the
@@ -67,6 +73,8 @@ struct TWLaunch {
     int32_t L;    // level of the walked axis
     int32_t B;    // block exponent along the walked axis
     int32_t ept;  // tile elements per thread (threads = 1024)
+    int32_t split = 2;  // 2: two-level walk; 3: three-level walk (L = TB + 2B, ept 1)
+    int32_t TB = 0;
     TileGeom g;   // tile axes
 };
 
@@ -144,12 +152,17 @@ inline hipError_t launch_batch(int op, int dtype, const BatchTask *dev_tasks, in
 #undef SGH_ROUTE
 
 bool pole_supported(int L, int B);
+bool pole3_supported(int L, int TB, int B);
+bool tw3_supported(int L, int TB, int B);
 // Threads per workgroup of the fused tile + walked-axis kernel, and the
 // (L, B, ept) combinations it is built for.
 constexpr int kTWThreads = 1024;
 bool tw_supported(int L, int B, int ept);
-// LDS rows staged at once by the fused kernel: 16 / ept rows of the tile.
+// LDS rows staged at once by the fused kernel: 16 / ept rows of the tile for
+// the two-level walk, 8 rows for the three-level walk (groups of 7 rows, so
+// two workgroups fit one CU's LDS).
 constexpr int tw_rows_per_batch(int ept) { return 16 / ept; }
+constexpr int kTW3Rows = 8;
 bool tile_ept_supported(int ept);
 bool batch_ept_supported(int ept);
 int max_lds_bytes();

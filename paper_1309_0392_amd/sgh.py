@@ -27,7 +27,8 @@ OK = 0
 ERR_ARG, ERR_DTYPE, ERR_ALIGN, ERR_OVERLAP, ERR_HIP, ERR_NOMEM, ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libsgh.so")
+# SGH_LIBRARY may name another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("SGH_LIBRARY") or os.path.join(_PKG, "libsgh.so")
 
 
 class SghGrid(ctypes.Structure):
@@ -77,6 +78,7 @@ def lib():
             "sgh_timing_enable": ([i32], ctypes.c_int),
             "sgh_set_pole_block": ([i32, i32], ctypes.c_int),
             "sgh_set_fusion": ([i32], ctypes.c_int),
+            "sgh_set_pole_split": ([i32, i32, i32, i32], ctypes.c_int),
             "sgh_timing_reset": ([], ctypes.c_int),
             "sgh_timing_report": ([ctypes.c_char_p, i32], ctypes.c_int),
         }
@@ -260,8 +262,20 @@ def set_pole_block(level: int, block_exponent: int):
 
 
 def set_fusion(level: int):
-    """1 (default): fuse the LDS-tile axes with one register-walked strided axis; 0: one launch per pass."""
+    """1 (default): fuse the LDS-tile axes with one register-walked strided axis; 2: fused, two-level
+    walk only; 0: one launch per pass."""
     _check(lib().sgh_set_fusion(int(level)), "sgh_set_fusion")
+
+
+def set_pole_split(level: int, top_exponent: int, block_exponent: int, prefetch: int = 0):
+    """Force the three-level register walk for strided poles of `level` (block_exponent 0 = default)."""
+    _check(lib().sgh_set_pole_split(int(level), int(top_exponent), int(block_exponent), int(prefetch)),
+           "sgh_set_pole_split")
+
+
+# (level, top exponent, block exponent) splits of the three-level pole walk and of the fused kernel
+POLE3_SPLITS = [(7, 1, 3), (8, 2, 3), (9, 3, 3), (10, 2, 4)]
+TW3_SPLITS = [(7, 1, 3), (8, 2, 3), (9, 3, 3)]
 
 
 # POLE_PAIRS: (level, block exponent) pairs of the register-resident pole kernel

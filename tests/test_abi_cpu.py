@@ -97,6 +97,7 @@ def test_schedules():
     # axis 0 in an LDS tile fused with axis 2 walked in registers; axis 1 strided
     assert kinds == [("tw", (0, 2)), ("pole", (1,))]
     assert [l.get("L") for l in s["launches"]] == [8, 9]
+    assert [(l["split"], l["TB"], l["B"]) for l in s["launches"]] == [(3, 2, 3), (3, 3, 3)]
     assert s["hbm_round_trips"] == 2
     d = sgh.schedule(sgh.OP_DEHIERARCHIZE, W.ANISO_3D)
     assert [tuple(l["axes"]) for l in d["launches"]] == [(0, 2), (1,)]
@@ -116,8 +117,8 @@ def test_schedules():
     assert lv[0]["kind"] == "level" and [l["lev"] for l in lv[:11]] == list(range(2, 13))
     assert lv[-1]["kind"] == "tile"
     # a walked axis that is not the last one (the last is too long for registers)
-    lv = sgh.schedule(sgh.OP_HIERARCHIZE, (10, 4, 9))["launches"]
-    assert [(l["kind"], tuple(l["axes"])) for l in lv] == [("tw", (0, 1)), ("pole", (2,))]
+    lv = sgh.schedule(sgh.OP_HIERARCHIZE, (10, 4, 11))["launches"]
+    assert [(l["kind"], tuple(l["axes"])) for l in lv] == [("tw", (0, 1))] + [("level", (2,))] * 10
 
 
 def test_fusion_switch():
@@ -135,3 +136,15 @@ def test_fusion_switch():
     assert sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D)["launches"][0]["kind"] == "tw"
     with pytest.raises(sgh.SghError):
         sgh.set_pole_block(9, 7)
+    with pytest.raises(sgh.SghError):
+        sgh.set_pole_split(9, 1, 4, 0)
+    try:
+        sgh.set_fusion(2)
+        s = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D)
+        assert (s["launches"][0]["kind"], s["launches"][0]["split"]) == ("tw", 2)
+        sgh.set_pole_split(9, 3, 3, 1)
+        s = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D)
+        assert (s["launches"][1]["split"], s["launches"][1]["prefetch"]) == (3, 1)
+    finally:
+        sgh.set_fusion(1)
+        sgh.set_pole_split(9, 0, 0, 0)

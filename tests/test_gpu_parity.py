@@ -84,7 +84,7 @@ def test_fp64_matches_oracle_bitwise_on_pole_and_tile_paths():
     differently)."""
     sgh.set_fusion(0)
     try:
-        for levels in [(7, 7), (10, 4, 3), (5, 9), (3, 11)]:
+        for levels in [(7, 7), (10, 4, 3), (5, 9), (3, 11), (4, 8), (2, 10, 2)]:
             x = W.uniform(levels, 5)
             for op in OPS:
                 got = gpu_run(op, x, levels)
@@ -104,28 +104,76 @@ def _tw_shape(ept, L, dtype):
     return (lead, mid, L)
 
 
-TW_COMBOS = [(2, 1), (3, 1), (4, 1), (5, 1), (6, 1), (7, 1), (8, 1), (2, 2), (3, 2), (4, 2), (5, 2), (6, 2),
-             (2, 4), (3, 4), (4, 4), (5, 4)]
+TW_COMBOS = [(2, 1), (3, 1), (4, 1), (5, 1), (6, 1), (7, 1), (8, 1), (9, 1), (2, 2), (3, 2), (4, 2), (5, 2),
+             (6, 2), (2, 4), (3, 4), (4, 4), (5, 4)]
 
 
+@pytest.mark.parametrize("fusion", [1, 2], ids=["default-walk", "two-level-walk"])
 @pytest.mark.parametrize("L,ept", TW_COMBOS)
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
-def test_fused_tile_walk(L, ept, dtype):
-    levels = _tw_shape(ept, L, dtype)
-    sched = sgh.schedule(sgh.OP_HIERARCHIZE, levels, sgh.F64 if dtype == np.float64 else sgh.F32)
-    tw = [l for l in sched["launches"] if l["kind"] == "tw"]
-    assert len(tw) == 1 and tw[0]["axes"] == [0, 2] and tw[0]["ept"] == ept and tw[0]["L"] == L, sched
-    x = W.uniform(levels, [23, L, ept], dtype)
-    x64 = x.astype(np.float64)
-    for op in OPS:
-        ref = ORACLE[op](x64, levels)
-        got = gpu_run(op, x, levels)
-        err = rel_err(op, x64, got, ref)
-        print("tw levels=%s ept=%d op=%s err=%.3e" % (levels, ept, OP_NAME[op], err), flush=True)
-        assert err <= TOL[dtype], (OP_NAME[op], err)
+def test_fused_tile_walk(L, ept, dtype, fusion):
+    """Fused tile + walked axis: every (walked level, tile elements per thread); the
+    three-level walk (levels 7-9, one element per thread) and the two-level walk."""
+    sgh.set_fusion(fusion)
+    try:
+        levels = _tw_shape(ept, L, dtype)
+        sched = sgh.schedule(sgh.OP_HIERARCHIZE, levels, sgh.F64 if dtype == np.float64 else sgh.F32)
+        tw = [l for l in sched["launches"] if l["kind"] == "tw" and l["axes"] == [0, 2]]
+        three = fusion == 1 and ept == 1 and (L, L - 6, 3) in sgh.TW3_SPLITS
+        two_level_built = L <= 8 and (ept == 1 or L <= 6)
+        if not three and not two_level_built:
+            assert not tw, sched  # no kernel walks this axis: it gets its own launch
+            return
+        assert len(tw) == 1 and tw[0]["axes"] == [0, 2] and tw[0]["ept"] == ept and tw[0]["L"] == L, sched
+        assert tw[0]["split"] == (3 if three else 2), sched
+        x = W.uniform(levels, [23, L, ept], dtype)
+        x64 = x.astype(np.float64)
+        for op in OPS:
+            ref = ORACLE[op](x64, levels)
+            got = gpu_run(op, x, levels)
+            err = rel_err(op, x64, got, ref)
+            print("tw levels=%s ept=%d split=%d op=%s err=%.3e" % (levels, ept, tw[0]["split"], OP_NAME[op], err),
+                  flush=True)
+            assert err <= TOL[dtype], (OP_NAME[op], err)
+    finally:
+        sgh.set_fusion(1)
 
 
-@pytest.mark.parametrize("levels", [(6, 6, 3, 5), (3, 4, 5, 5), (10, 4, 9), (10, 4, 3, 2), (5, 3, 2, 6, 2)], ids=ids)
+@pytest.mark.parametrize("L,TB,B", sgh.POLE3_SPLITS)
+@pytest.mark.parametrize("pf", [0, 1], ids=["nopf", "prefetch"])
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_every_pole3_split(L, TB, B, pf, dtype):
+    """Three-level register walk of a strided pole, at a wide and (where the grid
+    leaves the LDS tile) a 31-element stride."""
+    sgh.set_pole_split(L, TB, B, pf)
+    sgh.set_fusion(0)
+    cap = 8192 if dtype == np.float64 else 16384
+    leads = [(12,) if dtype == np.float64 else (13,)]
+    if 31 * ((1 << L) - 1) > cap:
+        leads.append((5,))
+    try:
+        for lead in leads:
+            levels = lead + (L,)
+            sched = sgh.schedule(sgh.OP_HIERARCHIZE, levels, sgh.F64 if dtype == np.float64 else sgh.F32)
+            pole = sched["launches"][1]
+            assert pole["kind"] == "pole" and pole["split"] == 3 and pole["TB"] == TB and pole["B"] == B
+            assert pole["prefetch"] == pf
+            x = W.uniform(levels, [25, L, pf], dtype)
+            x64 = x.astype(np.float64)
+            for op in OPS:
+                ref = ORACLE[op](x64, levels)
+                got = gpu_run(op, x, levels)
+                err = rel_err(op, x64, got, ref)
+                print("pole3 L=%d TB=%d B=%d pf=%d lead=%s op=%s err=%.3e" % (L, TB, B, pf, lead, OP_NAME[op], err),
+                      flush=True)
+                assert err <= TOL[dtype], (OP_NAME[op], err)
+    finally:
+        sgh.set_pole_split(L, 0, 0, 0)
+        sgh.set_fusion(1)
+
+
+@pytest.mark.parametrize("levels", [(6, 6, 3, 5), (3, 4, 5, 5), (10, 4, 9), (10, 4, 11), (10, 4, 3, 2),
+                                    (5, 3, 2, 6, 2)], ids=ids)
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
 def test_fused_tile_walk_layouts(levels, dtype):
     """Multi-axis tiles, a walked axis that is not the last one, and axes after it."""
