@@ -41,8 +41,8 @@ def parse():
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="use the library's default schedule instead of autotuning it first")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the schedule of the grid first (timed trial launches on scratch grids)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only copy a buffer of the workload's size (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -123,7 +123,7 @@ def main():
     gen_s = time.time() - t0
 
     tuned = {}
-    if not args.no_autotune:
+    if args.autotune:
         # time the candidate schedules on scratch grids of the same shape; the
         # one-shot calls below then use the chosen schedule (kept in-process)
         for op in (sgh.OP_HIERARCHIZE, sgh.OP_DEHIERARCHIZE, sgh.OP_ADJOINT):
@@ -204,7 +204,7 @@ def main():
         for bdt, bname in ((np.float64, "f64"), (np.float32, "f32")):
             xs = [torch.from_numpy(a).to(dev) for a in W.combination_values(lv, seed=3, dtype=bdt)]
             npts = sum(t.numel() for t in xs)
-            plan = sgh.Plan(sgh.OP_HIERARCHIZE, xs, lv, graph=True)
+            plan = sgh.Plan(sgh.OP_HIERARCHIZE, xs, lv, graph=True, autotune=True)
             plan.execute()
             ms_plan = time_region(torch, plan.execute, 50) / 50
 

@@ -166,6 +166,11 @@ int sgh_set_pole_split(int32_t level, int32_t top_exponent, int32_t block_expone
  * the same map.  Applies to schedules and plans built after the call. */
 int sgh_set_fusion(int32_t level);
 
+/* Which strided axis the fused launch walks when several qualify and no
+ * autotuned choice exists: 0 (default) the one with the smallest stride (each
+ * workgroup then streams one contiguous slab), 1 the one with the largest. */
+int sgh_set_walk_preference(int32_t pref);
+
 /* ---- measurement support ------------------------------------------------
  *
  * With timing on, every kernel the library launches is bracketed by HIP

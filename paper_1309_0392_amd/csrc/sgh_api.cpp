@@ -285,6 +285,7 @@ std::mutex g_override_mu;
 int g_pole_B_override[SGH_MAX_LEVEL + 1] = {};
 int g_pole3_override[SGH_MAX_LEVEL + 1] = {};  // 1 + TB * 100 + B * 10 + pf, 0 = none
 int g_fusion = 1;
+int g_walk_pref = 0;  // 0: smallest-stride walk candidate, 1: largest
 
 int pole_B_override(int L) {
     std::lock_guard<std::mutex> lk(g_override_mu);
@@ -455,8 +456,15 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
         if (o.walk >= 0 && walk_ok(g, m, Sm, o.walk)) {
             walk = o.walk;
         } else if (o.walk == -1) {
+            // default: the walk candidate with the smallest stride, so that a
+            // pencil is one contiguous slab of the grid
             auto c = walk_candidates(g);
-            if (!c.empty()) walk = c.front();
+            int pref = 0;
+            {
+                std::lock_guard<std::mutex> lk(g_override_mu);
+                pref = g_walk_pref;
+            }
+            if (!c.empty()) walk = pref == 1 ? c.front() : c.back();
         }
     }
     if (walk >= 0) {
@@ -531,6 +539,7 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
                 split = 3;
                 TB = tb3;
                 B = b3;
+                pf = 1;
             }
         }
         const int code = static_cast<size_t>(k) < o.pole_code.size() ? o.pole_code[static_cast<size_t>(k)] : 0;
@@ -1298,6 +1307,14 @@ int sgh_set_pole_split(int32_t level, int32_t top_exponent, int32_t block_expone
                     block_exponent);
     std::lock_guard<std::mutex> lk(g_override_mu);
     g_pole3_override[level] = 1 + top_exponent * 100 + block_exponent * 10 + prefetch;
+    return SGH_OK;
+}
+
+int sgh_set_walk_preference(int32_t pref) {
+    using namespace sgh;
+    if (pref < 0 || pref > 1) return fail(SGH_ERR_ARG, "walk preference %d outside 0..1", pref);
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    g_walk_pref = pref;
     return SGH_OK;
 }
 

@@ -79,6 +79,7 @@ def lib():
             "sgh_set_pole_block": ([i32, i32], ctypes.c_int),
             "sgh_set_fusion": ([i32], ctypes.c_int),
             "sgh_set_pole_split": ([i32, i32, i32, i32], ctypes.c_int),
+            "sgh_set_walk_preference": ([i32], ctypes.c_int),
             "sgh_timing_reset": ([], ctypes.c_int),
             "sgh_timing_report": ([ctypes.c_char_p, i32], ctypes.c_int),
         }
@@ -265,6 +266,11 @@ def set_fusion(level: int):
     """1 (default): fuse the LDS-tile axes with one register-walked strided axis; 2: fused, two-level
     walk only; 0: one launch per pass."""
     _check(lib().sgh_set_fusion(int(level)), "sgh_set_fusion")
+
+
+def set_walk_preference(pref: int):
+    """0 (default): walk the qualifying strided axis with the smallest stride; 1: the largest."""
+    _check(lib().sgh_set_walk_preference(int(pref)), "sgh_set_walk_preference")
 
 
 def set_pole_split(level: int, top_exponent: int, block_exponent: int, prefetch: int = 0):

@@ -94,16 +94,18 @@ def test_num_points():
 def test_schedules():
     s = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D)
     kinds = [(l["kind"], tuple(l["axes"])) for l in s["launches"]]
-    # axis 0 in an LDS tile fused with axis 2 walked in registers; axis 1 strided
-    assert kinds == [("tw", (0, 2)), ("pole", (1,))]
-    assert [l.get("L") for l in s["launches"]] == [8, 9]
-    assert [(l["split"], l["TB"], l["B"]) for l in s["launches"]] == [(3, 2, 3), (3, 3, 3)]
+    # axis 0 in an LDS tile fused with axis 1 walked in registers (each workgroup
+    # streams one contiguous plane); axis 2 strided
+    assert kinds == [("tw", (0, 1)), ("pole", (2,))]
+    assert [l.get("L") for l in s["launches"]] == [9, 8]
+    assert [(l["split"], l["TB"], l["B"]) for l in s["launches"]] == [(3, 3, 3), (3, 2, 3)]
+    assert s["launches"][1]["prefetch"] == 1
     assert s["hbm_round_trips"] == 2
     d = sgh.schedule(sgh.OP_DEHIERARCHIZE, W.ANISO_3D)
-    assert [tuple(l["axes"]) for l in d["launches"]] == [(0, 2), (1,)]
+    assert [tuple(l["axes"]) for l in d["launches"]] == [(2,), (0, 1)]
     s5 = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_5D)
     assert [(l["kind"], tuple(l["axes"])) for l in s5["launches"]] == [
-        ("tw", (0, 1, 4)), ("pole", (2,)), ("pole", (3,))]
+        ("tw", (0, 1, 2)), ("pole", (3,)), ("pole", (4,))]
     assert s5["launches"][0]["ept"] == 4 and s5["launches"][0]["tile"] == 63 * 63
     small = sgh.schedule(sgh.OP_HIERARCHIZE, W.SMALL_2D)
     assert [(l["kind"], tuple(l["axes"])) for l in small["launches"]] == [("tile", (0, 1))]
@@ -119,6 +121,8 @@ def test_schedules():
     # a walked axis that is not the last one (the last is too long for registers)
     lv = sgh.schedule(sgh.OP_HIERARCHIZE, (10, 4, 11))["launches"]
     assert [(l["kind"], tuple(l["axes"])) for l in lv] == [("tw", (0, 1))] + [("level", (2,))] * 10
+    lv = sgh.schedule(sgh.OP_HIERARCHIZE, (10, 11, 4))["launches"]
+    assert [(l["kind"], tuple(l["axes"])) for l in lv][0] == ("tw", (0, 2))
 
 
 def test_fusion_switch():

@@ -95,7 +95,8 @@ def test_fp64_matches_oracle_bitwise_on_pole_and_tile_paths():
 
 def _tw_shape(ept, L, dtype):
     """A grid whose schedule fuses a leading tile of 1023 / 2047 / 4095 points with a
-    walked strided axis of level L (the middle axis keeps the grid out of one tile)."""
+    walked strided axis of level L (the middle axis keeps the grid out of one tile;
+    the tests prefer walking the largest stride, i.e. axis 2)."""
     lead = {1: 10, 2: 11, 4: 12}[ept]
     cap = 8192 if dtype == np.float64 else 16384
     mid = 2
@@ -115,6 +116,7 @@ def test_fused_tile_walk(L, ept, dtype, fusion):
     """Fused tile + walked axis: every (walked level, tile elements per thread); the
     three-level walk (levels 7-9, one element per thread) and the two-level walk."""
     sgh.set_fusion(fusion)
+    sgh.set_walk_preference(1)
     try:
         levels = _tw_shape(ept, L, dtype)
         sched = sgh.schedule(sgh.OP_HIERARCHIZE, levels, sgh.F64 if dtype == np.float64 else sgh.F32)
@@ -137,6 +139,7 @@ def test_fused_tile_walk(L, ept, dtype, fusion):
             assert err <= TOL[dtype], (OP_NAME[op], err)
     finally:
         sgh.set_fusion(1)
+        sgh.set_walk_preference(0)
 
 
 @pytest.mark.parametrize("L,TB,B", sgh.POLE3_SPLITS)
