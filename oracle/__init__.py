@@ -13,9 +13,12 @@ Array convention: a grid of level vector ``(l_0, ..., l_{d-1})`` is a
 C-contiguous float64 array of shape ``(2**l_{d-1}-1, ..., 2**l_0-1)``; the last
 numpy axis is grid axis 0, the fastest-changing index (the paper's x_1).
 
-Parity status: every routine exported here is pinned by ``tests/test_oracle_pins.py``
-(hat basis, linear reproduction, dense hat-evaluation matrices, sine closed form,
-axis-order invariance, dense transpose, brute-force flop counts).
+Parity status: every routine exported here is pinned: the transforms by
+``tests/test_oracle_pins.py`` (hat basis, linear reproduction, dense hat-evaluation
+matrices, sine closed form, axis-order invariance, dense transpose, brute-force flop
+counts), the combination-technique gather / scatter by ``tests/test_oracle_combi.py``
+(coefficient identity, surpluses of one function, unit surpluses, and the round trip
+against the nodal combination formula sum_l c_l u_l).
 """
 from __future__ import annotations
 
@@ -167,3 +170,87 @@ def mults_reduced(levels) -> float:
 def num_points(levels) -> int:
     lv, d = _levels_arg(levels)
     return int(_load().oracle_num_points(d, lv))
+
+
+# ------------------------------------------------- combination technique ---
+def sparse_layout(levels_list):
+    """Sparse-grid storage of a combination set: every hierarchical subspace m
+    (m >= 1) contained in at least one grid, ordered by |m|_1, then
+    lexicographically (m_0 first); subspace m holds prod 2^(m_k - 1) points,
+    axis 0 fastest.  Returns (subspace levels (S, d) int array, offsets (S,),
+    total points)."""
+    d = len(levels_list[0])
+    subs = set()
+    for lv in levels_list:
+        ranges = [range(1, int(l) + 1) for l in lv]
+        stack = [()]
+        for r in ranges:
+            stack = [t + (v,) for t in stack for v in r]
+        subs.update(stack)
+    order = sorted(subs, key=lambda m: (sum(m), m))
+    sub_levels = np.array(order, dtype=np.int32).reshape(-1, d)
+    sizes = np.array([1 << (sum(m) - d) for m in order], dtype=np.int64)
+    offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    return sub_levels, offsets, int(sizes.sum())
+
+
+def _combi_args(xs, levels_list):
+    lib = _load()
+    d = len(levels_list[0])
+    arrays = [np.ascontiguousarray(x, dtype=np.float64) for x in xs]
+    for a, lv in zip(arrays, levels_list):
+        if tuple(a.shape) != shape_of(lv):
+            raise ValueError("grid shape does not match its levels")
+    ptrs = (ctypes.POINTER(ctypes.c_double) * len(arrays))(
+        *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrays])
+    lv = np.ascontiguousarray(np.array(levels_list, dtype=np.int32).reshape(-1))
+    return lib, d, arrays, ptrs, lv
+
+
+def combi_gather(xs, levels_list, coefs, layout=None) -> np.ndarray:
+    """Sparse-grid surpluses: sum over grids (in list order) of coef * grid surplus."""
+    lib, d, arrays, ptrs, lv = _combi_args(xs, levels_list)
+    sub, off, total = layout if layout is not None else sparse_layout(levels_list)
+    sub = np.ascontiguousarray(sub, dtype=np.int32)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    c = np.ascontiguousarray(coefs, dtype=np.float64)
+    out = np.zeros(total, dtype=np.float64)
+    f = lib.oracle_combi_gather
+    f.restype = ctypes.c_int
+    rc = f(len(arrays), ptrs, lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+           c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), d, sub.shape[0],
+           sub.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+           ctypes.c_int64(total), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise ValueError("oracle_combi_gather failed (%d)" % rc)
+    return out
+
+
+def combi_scatter(sparse, levels_list, layout=None):
+    """Grids whose every point holds the sparse grid's surplus at that point."""
+    xs = [np.zeros(shape_of(lv)) for lv in levels_list]
+    lib, d, arrays, ptrs, lv = _combi_args(xs, levels_list)
+    sub, off, total = layout if layout is not None else sparse_layout(levels_list)
+    sub = np.ascontiguousarray(sub, dtype=np.int32)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    sp = np.ascontiguousarray(sparse, dtype=np.float64)
+    if sp.size != total:
+        raise ValueError("sparse array has %d points, layout %d" % (sp.size, total))
+    f = lib.oracle_combi_scatter
+    f.restype = ctypes.c_int
+    rc = f(len(arrays), ptrs, lv.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), d, sub.shape[0],
+           sub.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+           sp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise ValueError("oracle_combi_scatter failed (%d)" % rc)
+    return arrays
+
+
+def combi_round_trip(xs, levels_list, coefs):
+    """Iterated combination technique step without a solver: hierarchize every
+    grid, gather the sparse grid, scatter it back, dehierarchize every grid."""
+    hs = [hierarchize(x, lv) for x, lv in zip(xs, levels_list)]
+    layout = sparse_layout(levels_list)
+    sp = combi_gather(hs, levels_list, coefs, layout)
+    back = combi_scatter(sp, levels_list, layout)
+    return [dehierarchize(b, lv) for b, lv in zip(back, levels_list)], sp

@@ -354,3 +354,103 @@ double oracle_hierarchize_adjoint_point(const double *g, int d, const int *level
     for (int k = 0; k < d; ++k) q[k] = pos[k];
     return adj_point_rec(g, d, level, q, pos, d - 1);
 }
+
+/* --- combination technique: gather and scatter of surpluses ---------------
+ *
+ * Hierarchization is the preprocessing step of the combination technique's
+ * communication phase (Section 2, "Hierarchization as preprocessing"): in the
+ * hierarchical basis a point that a combination grid lacks has surplus zero,
+ * so combining grids needs no interpolation.  The sparse grid's surplus at a
+ * hierarchical point is the coefficient-weighted sum of the surpluses of every
+ * combination grid that contains the point (Fig. 1: weights +1/-1 in 2-d).
+ *
+ * Sparse-grid storage: a list of hierarchical subspaces, each given by its
+ * level vector m (point i of axis k sits at odd position (2 i + 1) on level
+ * m_k, i = 0 .. 2^(m_k - 1) - 1) and stored densely with axis 0 fastest,
+ * starting at offsets[s].  A grid point at 1-based position p on a level-L
+ * axis has 1-d level m = L - log2(h), h its spacing (p an odd multiple of h),
+ * and odd index p / h on that level.
+ */
+
+/* 1-d level and odd index of position p on an axis of level L. */
+static void level_index(int64_t p, int L, int *m, int64_t *j)
+{
+    int lev = L;
+    while (p % 2 == 0) { p /= 2; --lev; }
+    *m = lev;
+    *j = p;
+}
+
+/* Subspace of level vector m in the list (linear search), or -1. */
+static int find_subspace(int d, const int *m, int nsub, const int *sub_levels)
+{
+    for (int s = 0; s < nsub; ++s) {
+        int eq = 1;
+        for (int k = 0; k < d && eq; ++k) eq = sub_levels[s * d + k] == m[k];
+        if (eq) return s;
+    }
+    return -1;
+}
+
+/* Element of the sparse array holding the point (m, j). */
+static int64_t sparse_index(int d, const int *m, const int64_t *j, const int64_t *offsets, int s)
+{
+    int64_t idx = 0, st = 1;
+    for (int k = 0; k < d; ++k) {
+        idx += ((j[k] - 1) / 2) * st;
+        st *= (int64_t)1 << (m[k] - 1);
+    }
+    return offsets[s] + idx;
+}
+
+/* Visit every point of grid g: compute its hierarchical point and call back. */
+typedef void (*combi_visit)(double *grid_val, double *sparse_val, double coef);
+
+static int combi_walk(int ngrids, double *const *grids, const int *levels, const double *coefs, int d,
+                      int nsub, const int *sub_levels, const int64_t *offsets, double *sparse, combi_visit fn)
+{
+    if (d < 1 || d > ORACLE_MAX_DIM) return -1;
+    for (int g = 0; g < ngrids; ++g) {
+        const int *L = levels + g * d;
+        const int64_t N = oracle_num_points(d, L);
+        int64_t pos[ORACLE_MAX_DIM], j[ORACLE_MAX_DIM];
+        int m[ORACLE_MAX_DIM];
+        for (int64_t e = 0; e < N; ++e) {
+            int64_t r = e;
+            for (int k = 0; k < d; ++k) {
+                const int64_t nk = points_of_level(L[k]);
+                pos[k] = r % nk + 1;
+                r /= nk;
+                level_index(pos[k], L[k], &m[k], &j[k]);
+            }
+            const int s = find_subspace(d, m, nsub, sub_levels);
+            if (s < 0) return -2; /* the sparse grid lacks a point of this grid */
+            fn(&grids[g][e], &sparse[sparse_index(d, m, j, offsets, s)], coefs ? coefs[g] : 1.0);
+        }
+    }
+    return 0;
+}
+
+static void visit_gather(double *grid_val, double *sparse_val, double coef) { *sparse_val += coef * *grid_val; }
+static void visit_scatter(double *grid_val, double *sparse_val, double coef)
+{
+    (void)coef;
+    *grid_val = *sparse_val;
+}
+
+/* sparse = sum over grids, in list order, of coef * surplus (sparse is
+ * zeroed first, sparse_size elements). */
+int oracle_combi_gather(int ngrids, double *const *grids, const int *levels, const double *coefs, int d,
+                        int nsub, const int *sub_levels, const int64_t *offsets, int64_t sparse_size,
+                        double *sparse)
+{
+    for (int64_t i = 0; i < sparse_size; ++i) sparse[i] = 0.0;
+    return combi_walk(ngrids, grids, levels, coefs, d, nsub, sub_levels, offsets, sparse, visit_gather);
+}
+
+/* Every grid point takes the sparse grid's surplus at its hierarchical point. */
+int oracle_combi_scatter(int ngrids, double *const *grids, const int *levels, int d, int nsub,
+                         const int *sub_levels, const int64_t *offsets, double *sparse)
+{
+    return combi_walk(ngrids, grids, levels, 0, d, nsub, sub_levels, offsets, sparse, visit_scatter);
+}
