@@ -128,6 +128,60 @@ int sgh_plan_set_data(sgh_plan *plan, const sgh_grid *grids, int32_t n);
 int sgh_plan_describe(const sgh_plan *plan, char *buf, int32_t len);
 void sgh_plan_destroy(sgh_plan *plan);
 
+/* ---- combination technique: sparse grid of a combination set ------------
+ *
+ * Hierarchization is what makes the combination technique's communication
+ * phase cheap (Section 2, "Hierarchization as preprocessing"): in the
+ * hierarchical basis a point that a combination grid does not hold has
+ * surplus zero, so the sparse grid's surplus at a point is the coefficient-
+ * weighted sum of the surpluses of the grids that hold it (Fig. 1 shows the
+ * +1/-1 weights in 2-d), with no interpolation.
+ *
+ * A combination object fixes a list of grids (one dim and one dtype; shapes,
+ * data pointers) and one coefficient per grid, and builds the sparse-grid
+ * layout on the host: every hierarchical subspace m (m_k >= 1) that lies in at
+ * least one grid (m <= l componentwise), ordered by |m|_1 and then
+ * lexicographically with m_0 compared first.  Subspace m stores its
+ * prod_k 2^(m_k - 1) points densely, axis 0 fastest; point i of axis k sits at
+ * the odd position 2 i + 1 of 1-d level m_k.  The sparse array is a device
+ * buffer of sgh_combi_sparse_points elements of the grids' dtype, owned by
+ * the caller.  The object does not own the grid buffers.
+ *
+ * flags: SGH_PLAN_GRAPH    sgh_combi_reduce replays one captured HIP graph
+ *                          (re-captured when the sparse pointer changes)
+ *        SGH_PLAN_AUTOTUNE autotune the hierarchize / dehierarchize plans.
+ * Errors: SGH_ERR_ARG for a null pointer, n < 1, or grids of mixed dim or
+ * dtype; descriptor errors as sgh_validate; SGH_ERR_UNSUPPORTED when the
+ * dense level table (prod_k max_l l_k entries) exceeds 2^26 entries.
+ * Calls on one object must not overlap in time (they share device state).
+ */
+typedef struct sgh_combi sgh_combi;
+
+int sgh_combi_create(sgh_combi **combi, const sgh_grid *grids, int32_t n, const double *coefs, uint32_t flags);
+/* Points of the sparse grid (length of the sparse array), -1 for null. */
+int64_t sgh_combi_sparse_points(const sgh_combi *combi);
+/* Number of subspaces S, -1 for null. */
+int32_t sgh_combi_num_subspaces(const sgh_combi *combi);
+/* Copies the layout to host arrays: sub_levels[S * dim] (level vector of
+ * subspace s at s * dim, axis 0 first) and offsets[S] (first element). */
+int sgh_combi_layout(const sgh_combi *combi, int32_t *sub_levels, int64_t *offsets);
+/* sparse[point] = sum over the grids holding the point, in list order, of
+ * coef * grid value (the grids must already hold surpluses).  Every element is
+ * written.  Products and sums are rounded separately, in the grids' dtype.
+ * Asynchronous on `stream` (NULL = default stream). */
+int sgh_combi_gather(sgh_combi *combi, void *sparse, void *stream);
+/* Every point of every grid takes the sparse grid's value at that point
+ * (overwrites all grid values).  Asynchronous on `stream`. */
+int sgh_combi_scatter(sgh_combi *combi, const void *sparse, void *stream);
+/* One step of the iterated combination technique without the solver
+ * (Section 2): hierarchize every grid, gather into `sparse`, scatter back,
+ * dehierarchize every grid.  Leaves the sparse surpluses in `sparse`. */
+int sgh_combi_reduce(sgh_combi *combi, void *sparse, void *stream);
+/* Repoint to new grid buffers of identical shapes (same n and order).
+ * Synchronizes the device first and drops a captured graph. */
+int sgh_combi_set_data(sgh_combi *combi, const sgh_grid *grids, int32_t n);
+void sgh_combi_destroy(sgh_combi *combi);
+
 /* ---- host utilities (no device access) ---------------------------------- */
 
 /* Validates descriptors exactly as the transforms do; touches no memory
@@ -135,6 +189,12 @@ void sgh_plan_destroy(sgh_plan *plan);
 int sgh_validate(const sgh_grid *grids, int32_t n);
 /* Number of stored points of a grid, or -1 on an invalid descriptor. */
 int64_t sgh_num_points(const sgh_grid *grid);
+/* Sparse-grid layout of a combination set, exactly as sgh_combi_create builds
+ * it (same checks on the grids; host only).  Writes the first min(S, capacity)
+ * subspaces to sub_levels[s * dim ..] and offsets[s] (either may be NULL), the
+ * subspace count S to *num_subspaces and the total points to *points. */
+int sgh_sparse_layout(const sgh_grid *grids, int32_t n, int32_t capacity, int32_t *sub_levels, int64_t *offsets,
+                      int32_t *num_subspaces, int64_t *points);
 /* Describes the launch schedule the library would use for one grid (JSON). */
 int sgh_schedule_describe(int32_t op, const sgh_grid *grid, char *buf, int32_t len);
 const char *sgh_error_string(int code);

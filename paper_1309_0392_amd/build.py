@@ -4,7 +4,8 @@
 
 Sources: csrc/sgh_kernels_<f64|f32>_<h|d|a>.hip (device code from the templates
 in csrc/sgh_kernels.inc, one unit per element type and operation, compiled in
-parallel), csrc/sgh_api.cpp (host side, C ABI from include/sgh.h).  Packed FP32 instructions are disabled for all device code.
+parallel), csrc/sgh_api.cpp (host side, C ABI from include/sgh.h), csrc/sgh_combi.cpp
+(combination-technique sparse grid: layout, gather / scatter, reduce).  Packed FP32 instructions are disabled for all device code.
 """
 from __future__ import annotations
 
@@ -27,6 +28,7 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-p
 
 UNITS = [("sgh_kernels_%s_%s.hip" % (t, o), ["-x", "hip"] + DEVICE) for t in ("f64", "f32") for o in "hda"]
 UNITS.append(("sgh_api.cpp", ["-x", "hip"] + DEVICE))
+UNITS.append(("sgh_combi.cpp", ["-x", "hip"] + DEVICE))
 
 
 def build(verbose: bool = True, out: str = LIB, defines=(), build_dir: str = BUILD) -> str:

@@ -751,6 +751,8 @@ void batch_default_tune(const DevInfo &di, int maxN, int ntasks, int dtype, Batc
 }
 
 }  // namespace
+
+int report_error(int code, const char *msg) { return fail(code, "%s", msg); }
 }  // namespace sgh
 
 struct sgh_plan {

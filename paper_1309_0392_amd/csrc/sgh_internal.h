@@ -168,3 +168,48 @@ bool batch_ept_supported(int ept);
 int max_lds_bytes();
 
 }  // namespace sgh
+
+namespace sgh {
+
+// ---------------------------------------------------------------------------
+// Combination technique: gather / scatter of surpluses between the grids of a
+// combination set and the sparse grid (one dtype per set).
+struct CombiGrid {
+    void *data;
+    int32_t L[kMaxDim];
+    int64_t st[kMaxDim];  // element stride per axis
+    int64_t n[kMaxDim];   // points per axis
+};
+
+// A work unit: up to 256 consecutive points of one subspace (gather) or of
+// one grid (scatter).
+struct CombiUnit {
+    int32_t owner;  // subspace (gather) or grid (scatter)
+    int32_t count;
+    int64_t start;
+};
+
+struct CombiLaunch {
+    int32_t d;
+    int32_t nunits;
+    const CombiGrid *grids;      // [ngrids]
+    const int32_t *sub_levels;   // [nsub * d]
+    const int64_t *sub_offsets;  // [nsub]
+    const int32_t *contrib_begin;  // [nsub + 1], gather: contributors of subspace s
+    const int32_t *contrib_grid;   // grid index per contributor, list order
+    const double *contrib_coef;    // coefficient per contributor
+    const int64_t *table;          // scatter: subspace offset by level vector, dense
+    int64_t tstride[kMaxDim];      // scatter: table stride per axis (levels 1..maxL)
+    const CombiUnit *units;
+    void *sparse;
+};
+
+// Records `msg` as the library's last error message; returns `code`.
+int report_error(int code, const char *msg);
+
+hipError_t launch_combi_gather_f64(const CombiLaunch &p, hipStream_t s);
+hipError_t launch_combi_gather_f32(const CombiLaunch &p, hipStream_t s);
+hipError_t launch_combi_scatter_f64(const CombiLaunch &p, hipStream_t s);
+hipError_t launch_combi_scatter_f32(const CombiLaunch &p, hipStream_t s);
+
+}  // namespace sgh

@@ -82,6 +82,18 @@ def lib():
             "sgh_set_walk_preference": ([i32], ctypes.c_int),
             "sgh_timing_reset": ([], ctypes.c_int),
             "sgh_timing_report": ([ctypes.c_char_p, i32], ctypes.c_int),
+            "sgh_combi_create": ([ctypes.POINTER(vp), G, i32, ctypes.POINTER(ctypes.c_double), u32],
+                                 ctypes.c_int),
+            "sgh_combi_sparse_points": ([vp], i64),
+            "sgh_combi_num_subspaces": ([vp], i32),
+            "sgh_combi_layout": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i64)], ctypes.c_int),
+            "sgh_combi_gather": ([vp, vp, vp], ctypes.c_int),
+            "sgh_combi_scatter": ([vp, vp, vp], ctypes.c_int),
+            "sgh_combi_reduce": ([vp, vp, vp], ctypes.c_int),
+            "sgh_combi_set_data": ([vp, G, i32], ctypes.c_int),
+            "sgh_combi_destroy": ([vp], None),
+            "sgh_sparse_layout": ([G, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i64)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -235,10 +247,102 @@ class Plan:
             pass
 
 
+# ------------------------------------------------------ combination technique
+class Combination:
+    """The sparse grid of a combination set (sgh_combi_*): gather of the grids'
+    surpluses into the sparse grid, scatter back, and the whole reduce step
+    (hierarchize, gather, scatter, dehierarchize)."""
+
+    def __init__(self, tensors, levels, coefs, graph: bool = True, autotune: bool = False):
+        import numpy as np
+        levels = _levels_list(tensors, levels)
+        self.levels = [tuple(int(x) for x in l) for l in levels]
+        self.n = len(tensors)
+        if len(coefs) != self.n:
+            raise ValueError("need one coefficient per grid")
+        self.dtype = tensors[0].dtype
+        self._arr = grid_array([describe_tensor(t, l) for t, l in zip(tensors, self.levels)])
+        self._coefs = (ctypes.c_double * self.n)(*[float(c) for c in coefs])
+        handle = ctypes.c_void_p()
+        flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0)
+        _check(lib().sgh_combi_create(ctypes.byref(handle), self._arr, self.n, self._coefs, flags),
+               "sgh_combi_create")
+        self._h = handle
+        self.sparse_points = int(lib().sgh_combi_sparse_points(self._h))
+        nsub = int(lib().sgh_combi_num_subspaces(self._h))
+        d = len(self.levels[0])
+        sub = np.zeros((nsub, d), dtype=np.int32)
+        off = np.zeros(nsub, dtype=np.int64)
+        _check(lib().sgh_combi_layout(self._h, sub.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), "sgh_combi_layout")
+        self.sub_levels, self.offsets = sub, off
+
+    def new_sparse(self):
+        """A device buffer for the sparse grid (uninitialized)."""
+        import torch
+        return torch.empty(self.sparse_points, dtype=self.dtype, device="cuda")
+
+    def _sparse_ptr(self, sparse):
+        if sparse.dtype != self.dtype or not sparse.is_cuda or not sparse.is_contiguous() \
+                or sparse.numel() != self.sparse_points:
+            raise ValueError("sparse buffer must be a contiguous %s device tensor of %d elements"
+                             % (self.dtype, self.sparse_points))
+        return ctypes.c_void_p(sparse.data_ptr())
+
+    def gather(self, sparse, stream=None):
+        _check(lib().sgh_combi_gather(self._h, self._sparse_ptr(sparse), _stream_handle(stream)),
+               "sgh_combi_gather")
+        return sparse
+
+    def scatter(self, sparse, stream=None):
+        _check(lib().sgh_combi_scatter(self._h, self._sparse_ptr(sparse), _stream_handle(stream)),
+               "sgh_combi_scatter")
+
+    def reduce(self, sparse, stream=None):
+        _check(lib().sgh_combi_reduce(self._h, self._sparse_ptr(sparse), _stream_handle(stream)),
+               "sgh_combi_reduce")
+        return sparse
+
+    def set_data(self, tensors):
+        if len(tensors) != self.n:
+            raise ValueError("set has %d grids, got %d" % (self.n, len(tensors)))
+        self._arr = grid_array([describe_tensor(t, l) for t, l in zip(tensors, self.levels)])
+        _check(lib().sgh_combi_set_data(self._h, self._arr, self.n), "sgh_combi_set_data")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().sgh_combi_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # --------------------------------------------------------------- host utils
 def validate(grids: Sequence[SghGrid]) -> int:
     """sgh_validate on raw descriptors (host only); returns the code."""
     return lib().sgh_validate(grid_array(grids) if grids else None, len(grids))
+
+
+def sparse_layout(levels_list, dtype: int = F64):
+    """Host-side sparse-grid layout of a level set (sgh_sparse_layout):
+    (subspace levels (S, d) int32, offsets (S,) int64, total points)."""
+    import numpy as np
+    descs = grid_array([make_grid(l, dtype, 0) for l in levels_list])
+    n = len(levels_list)
+    nsub, pts = ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().sgh_sparse_layout(descs, n, 0, None, None, ctypes.byref(nsub), ctypes.byref(pts)),
+           "sgh_sparse_layout")
+    d = len(levels_list[0])
+    sub = np.zeros((nsub.value, d), dtype=np.int32)
+    off = np.zeros(nsub.value, dtype=np.int64)
+    _check(lib().sgh_sparse_layout(descs, n, nsub.value, sub.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(nsub),
+                                   ctypes.byref(pts)), "sgh_sparse_layout")
+    return sub, off, int(pts.value)
 
 
 def num_points(levels, dtype: int = F64) -> int:
