@@ -12,9 +12,10 @@ per-kernel durations behind the roofline figure.
 
 Prints one JSON line.  `value` is points/s of the whole job (one GPU).
 Extra fields: the inverse and the transpose on the same grid, the batched
-combination-technique set (589 grids, one graph-captured persistent launch)
-versus a loop of per-grid calls, a measured copy roof, the roofline of the
-dominant kernel and the CPU oracle timed on the host.
+combination-technique set (589 grids, one launch) versus a loop of per-grid
+calls, the sparse grid of that set (gather, scatter, reduce step) and the
+gather / scatter bandwidth on the d=4, n=15 set, a measured copy roof, the
+roofline of the dominant kernel and the CPU oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -218,6 +219,39 @@ def main():
                                         "per_grid_loop_ms": ms_loop, "speedup_vs_per_grid": ms_loop / ms_plan,
                                         "plan": plan.describe()["batches"]}
             plan.close()
+        # combination technique: sparse grid of the d=4, n=10 set (gather, scatter,
+        # and the solver-free reduce step hierarchize -> gather -> scatter -> dehierarchize)
+        xs = [torch.from_numpy(a).to(dev) for a in W.combination_values(lv, seed=3)]
+        npts = sum(t.numel() for t in xs)
+        comb = sgh.Combination(xs, lv, W.combination_set()[1], graph=True)
+        sp = comb.new_sparse()
+        ms_g = time_region(torch, lambda: comb.gather(sp), 50) / 50
+        ms_s = time_region(torch, lambda: comb.scatter(sp), 50) / 50
+        ms_r = time_region(torch, lambda: comb.reduce(sp), 20) / 20
+        extras["combination_d4n10_f64"] = {
+            "grids": len(lv), "grid_points": npts, "sparse_points": comb.sparse_points,
+            "gather_ms": ms_g, "scatter_ms": ms_s, "reduce_ms": ms_r,
+            "reduce_grid_points_per_s": npts / (ms_r * 1e-3)}
+        comb.close()
+        del xs, sp
+        # the same on the d=4, n=15 set (2059 grids, 1.1 GB FP64): gather / scatter bandwidth
+        lv15, c15 = W.combination_set(4, 15)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(5)
+        xs = [torch.rand(W.shape_of(l), dtype=torch.float64, device=dev, generator=gen) for l in lv15]
+        npts = sum(t.numel() for t in xs)
+        comb = sgh.Combination(xs, lv15, c15, graph=False)
+        sp = comb.new_sparse()
+        ms_g = time_region(torch, lambda: comb.gather(sp), 10) / 10
+        ms_s = time_region(torch, lambda: comb.scatter(sp), 10) / 10
+        algo = (npts + comb.sparse_points) * 8.0  # every grid point read or written once, sparse once
+        extras["combination_d4n15_f64"] = {
+            "grids": len(lv15), "grid_points": npts, "sparse_points": comb.sparse_points,
+            "gather_ms": ms_g, "scatter_ms": ms_s,
+            "gather_GBps_algorithmic": algo / (ms_g * 1e-3) / 1e9,
+            "scatter_GBps_algorithmic": algo / (ms_s * 1e-3) / 1e9}
+        comb.close()
+        del xs, sp
         out["extras"] = extras
 
     if not args.no_cpu_baseline:

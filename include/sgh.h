@@ -100,12 +100,14 @@ int sgh_transform(int32_t op, const sgh_grid *grids, int32_t n, void *stream);
  * A plan fixes an operation and a list of grids (shapes, dtypes and data
  * pointers), builds a device task list and, with SGH_PLAN_GRAPH, captures
  * all of its launches into one HIP graph.  Grids that fit the on-chip tile
- * are transformed by one persistent kernel launch that pops whole grids from
- * the task list (largest first); larger grids get their own launches, captured
- * in the same graph.  This is the coarse "all combination grids in parallel"
+ * are transformed by one kernel launch with one workgroup per grid (largest
+ * grids first), each grid loaded into LDS, transformed along all axes and
+ * stored once; larger grids get their own launches, captured in the same graph.  This is the coarse "all combination grids in parallel"
  * level of the combination technique (Section 2).
  *
- * flags: SGH_PLAN_GRAPH   capture into a hipGraph at creation
+ * flags: SGH_PLAN_GRAPH   capture into a hipGraph at creation when the plan
+ *                          needs more than one launch (a single launch is
+ *                          issued directly)
  *        SGH_PLAN_AUTOTUNE time candidate tile configurations on scratch
  *                          buffers at creation and keep the fastest (results
  *                          are cached per device, op, dtype and level set).

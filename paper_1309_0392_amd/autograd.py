@@ -51,7 +51,7 @@ def _plan(op: int, levels: List[Tuple[int, ...]], tensors) -> "sgh.Plan":
 
 
 class HierarchizeBatch(torch.autograd.Function):
-    """All grids of a combination set in one batched plan (one persistent launch)."""
+    """All grids of a combination set in one batched plan (one launch for the grids that fit on chip)."""
 
     @staticmethod
     def forward(ctx, levels: Tuple[Tuple[int, ...], ...], *us: torch.Tensor):

@@ -721,7 +721,6 @@ struct BatchGroup {
     std::vector<int> grid_idx;  // into the plan's grid list, launch order (LPT)
     BatchTune tune;
     BatchTask *dev_tasks = nullptr;
-    uint32_t *dev_counters = nullptr;
 };
 
 struct PlanLarge {
@@ -744,10 +743,10 @@ void batch_default_tune(const DevInfo &di, int maxN, int ntasks, int dtype, Batc
     t->nt = nt;
     t->ept = ept;
     t->lds_bytes = std::max<int>(static_cast<int>(maxN * esize_of(dtype)), 16);
-    const int by_lds = std::max(1, di.lds_per_cu / t->lds_bytes);
-    const int by_waves = std::max(1, 32 / (nt / 64));
-    const int per_cu = std::min({by_lds, by_waves, 8});
-    t->nwg = std::max(1, std::min(ntasks, per_cu * di.cus));
+    // one workgroup per grid: the dispatcher hands out grids as workgroups
+    // retire (largest first), which needs no shared queue counter
+    (void)di;
+    t->nwg = std::max(1, ntasks);
 }
 
 }  // namespace
@@ -787,8 +786,8 @@ hipError_t plan_launch_all(sgh_plan *p, hipStream_t st) {
         TimerScope ts(std::string(p->op == 0 ? "hier" : p->op == 1 ? "dehier" : "adjoint") +
                           (bg.dtype == SGH_F64 ? "_f64" : "_f32") + "_batch",
                       st);
-        hipError_t e = launch_batch(p->op, bg.dtype, bg.dev_tasks, static_cast<int32_t>(bg.grid_idx.size()),
-                                    bg.dev_counters, bg.tune, st);
+        hipError_t e =
+            launch_batch(p->op, bg.dtype, bg.dev_tasks, static_cast<int32_t>(bg.grid_idx.size()), bg.tune, st);
         if (e != hipSuccess) return e;
     }
     for (auto &lg : p->large)
@@ -887,23 +886,20 @@ int autotune_group(sgh_plan *p, BatchGroup &bg) {
         off += t.N;
     }
     BatchTask *dtasks = nullptr;
-    uint32_t *dcnt = nullptr;
     e = hipMalloc(&dtasks, tasks.size() * sizeof(BatchTask));
-    if (e == hipSuccess) e = hipMalloc(&dcnt, 2 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemcpy(dtasks, tasks.data(), tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(dcnt, 0, 2 * sizeof(uint32_t));
     hipStream_t st = nullptr;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     int best_nt = 256;
     float best = 1e30f;
     if (e == hipSuccess) {
-        for (int nt : {128, 256, 512}) {
+        for (int nt : {128, 256, 512, 1024}) {
             BatchTune t;
             batch_default_tune(di, maxN, static_cast<int>(tasks.size()), bg.dtype, &t, nt);
-            if (t.nt != nt) continue;
+            if (t.nt != nt || (nt == 1024 && t.ept > 8)) continue;
             const float ms = time_median(
                 [&](hipStream_t s) {
-                    return launch_batch(p->op, bg.dtype, dtasks, static_cast<int32_t>(tasks.size()), dcnt, t, s);
+                    return launch_batch(p->op, bg.dtype, dtasks, static_cast<int32_t>(tasks.size()), t, s);
                 },
                 st, 5);
             if (ms < best) {
@@ -914,7 +910,6 @@ int autotune_group(sgh_plan *p, BatchGroup &bg) {
     }
     if (st) (void)hipStreamDestroy(st);
     if (dtasks) (void)hipFree(dtasks);
-    if (dcnt) (void)hipFree(dcnt);
     (void)hipFree(scratch);
     if (e != hipSuccess) return hip_fail(e, "autotune");
     batch_default_tune(di, maxN, static_cast<int>(bg.grid_idx.size()), bg.dtype, &bg.tune, best_nt);
@@ -1062,7 +1057,6 @@ int autotune_large(sgh_plan *p, PlanLarge &lg) {
 void plan_free(sgh_plan *p) {
     for (auto &bg : p->groups) {
         if (bg.dev_tasks) (void)hipFree(bg.dev_tasks);
-        if (bg.dev_counters) (void)hipFree(bg.dev_counters);
     }
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -1190,17 +1184,6 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
         batch_default_tune(di, maxN, static_cast<int>(v.size()), bg.dtype, &bg.tune);
         hipError_t e = hipMalloc(&bg.dev_tasks, v.size() * sizeof(BatchTask));
         if (e != hipSuccess) return hip_fail(e, "task list");
-        e = hipMalloc(&bg.dev_counters, 2 * sizeof(uint32_t));
-        if (e != hipSuccess) {
-            (void)hipFree(bg.dev_tasks);
-            return hip_fail(e, "counters");
-        }
-        e = hipMemset(bg.dev_counters, 0, 2 * sizeof(uint32_t));
-        if (e != hipSuccess) {
-            (void)hipFree(bg.dev_tasks);
-            (void)hipFree(bg.dev_counters);
-            return hip_fail(e, "counters");
-        }
         p->groups.push_back(bg);
     }
     if (flags & SGH_PLAN_AUTOTUNE) {
@@ -1215,7 +1198,11 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
     }
     rc = plan_upload(p.get());
     if (rc) return rc;
-    if (flags & SGH_PLAN_GRAPH) {
+    // a single launch goes out directly: replaying a one-node graph measured
+    // slower than the launch it holds
+    size_t launches = p->groups.size();
+    for (const auto &lg : p->large) launches += lg.steps.size();
+    if ((flags & SGH_PLAN_GRAPH) && launches > 1) {
         rc = plan_capture(p.get());
         if (rc) return rc;
     }

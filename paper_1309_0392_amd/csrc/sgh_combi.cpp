@@ -40,8 +40,11 @@ struct sgh_combi {
     int32_t *d_sub_levels = nullptr;
     int64_t *d_sub_offsets = nullptr;
     int32_t *d_cbegin = nullptr;
-    int32_t *d_cgrid = nullptr;
+    std::vector<int32_t> csub, cgrid;  // subspace and grid of each contribution
+    int64_t *d_caddr = nullptr;
+    int64_t *d_cmul = nullptr;
     double *d_ccoef = nullptr;
+    int32_t fast32 = 0;
     int64_t *d_table = nullptr;
     sgh::CombiUnit *d_gunits = nullptr;
     sgh::CombiUnit *d_sunits = nullptr;
@@ -61,7 +64,7 @@ namespace {
 void combi_free(sgh_combi *c) {
     for (void *p : {static_cast<void *>(c->d_grids), static_cast<void *>(c->d_sub_levels),
                     static_cast<void *>(c->d_sub_offsets), static_cast<void *>(c->d_cbegin),
-                    static_cast<void *>(c->d_cgrid), static_cast<void *>(c->d_ccoef), static_cast<void *>(c->d_table),
+                    static_cast<void *>(c->d_caddr), static_cast<void *>(c->d_cmul), static_cast<void *>(c->d_ccoef), static_cast<void *>(c->d_table),
                     static_cast<void *>(c->d_gunits), static_cast<void *>(c->d_sunits)})
         if (p) (void)hipFree(p);
     if (c->hier) sgh_plan_destroy(c->hier);
@@ -85,8 +88,19 @@ hipError_t upload(V **dst, const std::vector<V> &src) {
     return e;
 }
 
-std::vector<CombiGrid> grid_table(const sgh_combi &c) {
+// x / n as a multiply and a shift for 0 <= x < 2^31: with s = ceil(log2 n)
+// and magic = floor(2^(32+s) / n) + 1 < 2^33, the error of x * magic / 2^(32+s)
+// against x / n is below x / 2^(32+s) < 2^-(s+1) <= 1 / (2n), so the floor is exact.
+void division_magic(int64_t n, uint64_t *magic, int32_t *shift) {
+    int sh = 0;
+    while ((int64_t(1) << sh) < n) ++sh;
+    *magic = static_cast<uint64_t>((static_cast<unsigned __int128>(1) << (32 + sh)) / static_cast<uint64_t>(n)) + 1;
+    *shift = 32 + sh;
+}
+
+std::vector<CombiGrid> grid_table(sgh_combi &c) {
     std::vector<CombiGrid> out;
+    c.fast32 = 1;
     for (const auto &g : c.grids) {
         CombiGrid cg{};
         cg.data = g.data;
@@ -95,11 +109,37 @@ std::vector<CombiGrid> grid_table(const sgh_combi &c) {
             cg.L[k] = g.level[k];
             cg.n[k] = (int64_t(1) << g.level[k]) - 1;
             cg.st[k] = st;
+            division_magic(cg.n[k], &cg.magic[k], &cg.mshift[k]);
             st *= cg.n[k];
         }
+        if (st >= (int64_t(1) << 31)) c.fast32 = 0;
         out.push_back(cg);
     }
     return out;
+}
+
+// Per contribution (subspace m, grid g): the grid's base address shifted by
+// -sum_k st_k elements, and the element step 2^(L_k - m_k) st_k per odd index
+// along axis k, so that the point with odd indices j sits at
+// base + sum_k j_k * step_k.
+hipError_t upload_contrib(sgh_combi *c) {
+    const int d = c->d;
+    const int64_t esize = c->dtype == SGH_F64 ? 8 : 4;
+    std::vector<int64_t> addr(c->cgrid.size()), mul(c->cgrid.size() * static_cast<size_t>(d));
+    for (size_t i = 0; i < c->cgrid.size(); ++i) {
+        const sgh_grid &g = c->grids[static_cast<size_t>(c->cgrid[i])];
+        const int32_t *m = &c->sub_levels[static_cast<size_t>(c->csub[i]) * static_cast<size_t>(d)];
+        int64_t st = 1, sst = 0;
+        for (int k = 0; k < d; ++k) {
+            mul[i * static_cast<size_t>(d) + static_cast<size_t>(k)] = (int64_t(1) << (g.level[k] - m[k])) * st;
+            sst += st;
+            st *= (int64_t(1) << g.level[k]) - 1;
+        }
+        addr[i] = static_cast<int64_t>(reinterpret_cast<uintptr_t>(g.data)) - sst * esize;
+    }
+    hipError_t e = upload(&c->d_caddr, addr);
+    if (e == hipSuccess) e = upload(&c->d_cmul, mul);
+    return e;
 }
 
 CombiLaunch launch_of(const sgh_combi &c, bool gather, void *sparse) {
@@ -110,8 +150,10 @@ CombiLaunch launch_of(const sgh_combi &c, bool gather, void *sparse) {
     p.sub_levels = c.d_sub_levels;
     p.sub_offsets = c.d_sub_offsets;
     p.contrib_begin = c.d_cbegin;
-    p.contrib_grid = c.d_cgrid;
+    p.contrib_addr = c.d_caddr;
+    p.contrib_mul = c.d_cmul;
     p.contrib_coef = c.d_ccoef;
+    p.fast32 = c.fast32;
     p.table = c.d_table;
     for (int k = 0; k < SGH_MAX_DIM; ++k) p.tstride[k] = c.tstride[k];
     p.units = gather ? c.d_gunits : c.d_sunits;
@@ -187,8 +229,11 @@ int combi_build(sgh_combi *c) {
     }
     c->total = off;
     // contributors (grid list order) and gather units
-    std::vector<int32_t> cbegin, cgrid;
+    std::vector<int32_t> cbegin;
+    std::vector<int32_t> &cgrid = c->cgrid;
     std::vector<double> ccoef;
+    cgrid.clear();
+    c->csub.clear();
     std::vector<CombiUnit> gunits;
     for (size_t s = 0; s < order.size(); ++s) {
         cbegin.push_back(static_cast<int32_t>(cgrid.size()));
@@ -197,6 +242,7 @@ int combi_build(sgh_combi *c) {
             for (int k = 0; k < d && in; ++k) in = order[s][static_cast<size_t>(k)] <= c->grids[g].level[k];
             if (in) {
                 cgrid.push_back(static_cast<int32_t>(g));
+                c->csub.push_back(static_cast<int32_t>(s));
                 ccoef.push_back(c->coefs[g]);
             }
         }
@@ -235,7 +281,7 @@ int combi_build(sgh_combi *c) {
     if (e == hipSuccess) e = upload(&c->d_sub_levels, c->sub_levels);
     if (e == hipSuccess) e = upload(&c->d_sub_offsets, c->sub_offsets);
     if (e == hipSuccess) e = upload(&c->d_cbegin, cbegin);
-    if (e == hipSuccess) e = upload(&c->d_cgrid, cgrid);
+    if (e == hipSuccess) e = upload_contrib(c);
     if (e == hipSuccess) e = upload(&c->d_ccoef, ccoef);
     if (e == hipSuccess) e = upload(&c->d_table, table);
     if (e == hipSuccess) e = upload(&c->d_gunits, gunits);
@@ -355,6 +401,7 @@ int sgh_combi_set_data(sgh_combi *c, const sgh_grid *grids, int32_t n) {
     if (rc) return rc;
     for (int i = 0; i < n; ++i) c->grids[static_cast<size_t>(i)].data = grids[i].data;
     hipError_t e = upload(&c->d_grids, grid_table(*c));
+    if (e == hipSuccess) e = upload_contrib(c);
     if (e != hipSuccess) return cfail(SGH_ERR_HIP, hipGetErrorString(e));
     drop_graph(c);
     return SGH_OK;

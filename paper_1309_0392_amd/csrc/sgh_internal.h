@@ -111,8 +111,8 @@ struct BatchTune {
     hipError_t launch_pole_##SUF(const PoleLaunch &p, const PoleTune &t, hipStream_t s);              \
     hipError_t launch_level_##SUF(const LevelLaunch &p, hipStream_t s);                              \
     hipError_t launch_tw_##SUF(const TWLaunch &p, hipStream_t s);                                     \
-    hipError_t launch_batch_##SUF(const BatchTask *dev_tasks, int32_t ntasks, uint32_t *dev_counters, \
-                                  const BatchTune &t, hipStream_t s);
+    hipError_t launch_batch_##SUF(const BatchTask *dev_tasks, int32_t ntasks, const BatchTune &t,    \
+                                  hipStream_t s);
 SGH_DECLARE_LAUNCHERS(f64_h)
 SGH_DECLARE_LAUNCHERS(f64_d)
 SGH_DECLARE_LAUNCHERS(f64_a)
@@ -145,9 +145,9 @@ inline hipError_t launch_level(int op, int dtype, const LevelLaunch &p, hipStrea
     SGH_ROUTE(launch_level, p, s);
 }
 inline hipError_t launch_tw(int op, int dtype, const TWLaunch &p, hipStream_t s) { SGH_ROUTE(launch_tw, p, s); }
-inline hipError_t launch_batch(int op, int dtype, const BatchTask *dev_tasks, int32_t ntasks,
-                               uint32_t *dev_counters, const BatchTune &t, hipStream_t s) {
-    SGH_ROUTE(launch_batch, dev_tasks, ntasks, dev_counters, t, s);
+inline hipError_t launch_batch(int op, int dtype, const BatchTask *dev_tasks, int32_t ntasks, const BatchTune &t,
+                               hipStream_t s) {
+    SGH_ROUTE(launch_batch, dev_tasks, ntasks, t, s);
 }
 #undef SGH_ROUTE
 
@@ -179,27 +179,35 @@ struct CombiGrid {
     int32_t L[kMaxDim];
     int64_t st[kMaxDim];  // element stride per axis
     int64_t n[kMaxDim];   // points per axis
+    // x / n[k] == (x * magic[k]) >> mshift[k] for 0 <= x < 2^31 (magic < 2^33)
+    uint64_t magic[kMaxDim];
+    int32_t mshift[kMaxDim];
 };
 
-// A work unit: up to 256 consecutive points of one subspace (gather) or of
-// one grid (scatter).
+// A work unit: 2^e consecutive points of one subspace (gather; at most
+// 256), or up to 256 consecutive points of one grid (scatter).
 struct CombiUnit {
     int32_t owner;  // subspace (gather) or grid (scatter)
     int32_t count;
     int64_t start;
 };
 
+// Products staged in LDS per gather chunk (pairs of point and contributor).
+constexpr int kCombiPairs = 2048;
+
 struct CombiLaunch {
     int32_t d;
     int32_t nunits;
-    const CombiGrid *grids;      // [ngrids]
-    const int32_t *sub_levels;   // [nsub * d]
-    const int64_t *sub_offsets;  // [nsub]
-    const int32_t *contrib_begin;  // [nsub + 1], gather: contributors of subspace s
-    const int32_t *contrib_grid;   // grid index per contributor, list order
+    const CombiGrid *grids;        // [ngrids]
+    const int32_t *sub_levels;     // [nsub * d]
+    const int64_t *sub_offsets;    // [nsub]
+    const int32_t *contrib_begin;  // [nsub + 1], gather: contributors of subspace s, grid-list order
+    const int64_t *contrib_addr;   // byte address of the contributor's data minus sum_k st_k elements
+    const int64_t *contrib_mul;    // [ncontrib * d]: elements per odd-index step, 2^(L_k - m_k) * st_k
     const double *contrib_coef;    // coefficient per contributor
     const int64_t *table;          // scatter: subspace offset by level vector, dense
     int64_t tstride[kMaxDim];      // scatter: table stride per axis (levels 1..maxL)
+    int32_t fast32;                // scatter: every grid has fewer than 2^31 points
     const CombiUnit *units;
     void *sparse;
 };

@@ -204,7 +204,7 @@ def hierarchize_adjoint(tensors, levels, stream=None):
 
 # -------------------------------------------------------------------- plans
 class Plan:
-    """A batched plan (sgh_plan_*): one persistent launch for all grids that
+    """A batched plan (sgh_plan_*): one launch (one workgroup per grid) for all grids that
     fit on chip, captured with the launches of larger grids into a HIP graph."""
 
     def __init__(self, op: int, tensors, levels, graph: bool = True, autotune: bool = False):
