@@ -220,6 +220,17 @@ int sgh_set_pole_block(int32_t level, int32_t block_exponent);
  * no kernel for. */
 int sgh_set_pole_split(int32_t level, int32_t top_exponent, int32_t block_exponent, int32_t prefetch);
 
+/* Tuning knob for poles too long for one pass (contiguous axes beyond the LDS
+ * tile, strided axes beyond the register kernels), which are cut into dyadic
+ * blocks: the block boundaries are the coarse points, transformed in later
+ * launches on a lattice of spacing 2^(sum of the earlier spans) (Section 3's
+ * binary-tree predecessors of a block's interior lie in the block or on its
+ * boundary).  `fine` is the span exponent of the first launch, `coarse` that of
+ * the later ones; each is capped to what fits a 64 KiB tile; 0 restores the
+ * defaults (a 32 KiB tile first, then spans of 2^7).  Applies to schedules and
+ * plans built after the call. */
+int sgh_set_split_spans(int32_t fine, int32_t coarse);
+
 /* Schedule switch: level 1 (default) fuses the leading LDS-tile axes with one
  * strided axis walked in registers into a single launch (one HBM round trip
  * for both); level 2 does the same but keeps the walk two-level; level 0 keeps

@@ -268,13 +268,14 @@ void timing_drain_locked() {
 // ---------------------------------------------------------------------------
 // Schedule of one grid: a list of launches, applied in order.
 struct Step {
-    enum Kind { TILE, POLE, LEVEL, TW } kind = TILE;
+    enum Kind { TILE, POLE, LEVEL, TW, SPLIT } kind = TILE;
     TileLaunch tile{};
     TileTune ttune{};
     PoleLaunch pole{};
     PoleTune ptune{};
     LevelLaunch level{};
     TWLaunch tw{};
+    SplitLaunch split{};
     std::vector<int> axes;  // axes (of the reduced geometry) this launch transforms
     int key = 0;            // largest axis covered; orders the inverse/transpose schedule
 };
@@ -286,6 +287,8 @@ int g_pole_B_override[SGH_MAX_LEVEL + 1] = {};
 int g_pole3_override[SGH_MAX_LEVEL + 1] = {};  // 1 + TB * 100 + B * 10 + pf, 0 = none
 int g_fusion = 1;
 int g_walk_pref = 0;  // 0: smallest-stride walk candidate, 1: largest
+int g_split_fine = 0;    // block span exponent of the first split phase, 0 = largest that fits
+int g_split_coarse = 0;  // the same for the later phases, 0 = default
 
 int pole_B_override(int L) {
     std::lock_guard<std::mutex> lk(g_override_mu);
@@ -445,6 +448,45 @@ std::vector<int> walk_candidates(const Geom &g) {
     return c;
 }
 
+// Launches of the dyadic split of axis k: phases with lattice exponents
+// E = 0, B0, B0 + B1, ... until the whole remaining pole fits one block;
+// fine to coarse for the hierarchization, coarse to fine otherwise.
+void split_steps(int op, const Geom &g, int k, std::vector<Step> *steps) {
+    const int64_t S = g.st[k];
+    int W = 1;
+    while (W < 64 && W < S) W <<= 1;
+    const int esize = g.dtype == SGH_F64 ? 8 : 4;
+    const int bmax = split_max_span(W, esize);
+    // 32 KiB tiles: four or five workgroups per CU keep enough loads in flight
+    int fine = std::max(1, bmax - 1), coarse = std::min(bmax, 7);
+    {
+        std::lock_guard<std::mutex> lk(g_override_mu);
+        if (g_split_fine > 0) fine = std::min(bmax, g_split_fine);
+        if (g_split_coarse > 0) coarse = std::min(bmax, g_split_coarse);
+    }
+    std::vector<Step> phases;
+    for (int E = 0; E < g.L[k];) {
+        Step s;
+        s.kind = Step::SPLIT;
+        s.axes = {k};
+        s.key = k;
+        s.split.data = g.data;
+        s.split.S = S;
+        s.split.outer = g.N / (g.n[k] * S);
+        s.split.L = g.L[k];
+        s.split.E = E;
+        // the coarse phases work on few points: narrow blocks spread them over
+        // many workgroups
+        s.split.Bs = std::min(E == 0 ? fine : coarse, g.L[k] - E);
+        s.split.W = W;
+        E += s.split.Bs;
+        // a lattice of one point (the root) changes only under the transpose
+        if (op == SGH_OP_ADJOINT || g.L[k] - s.split.E > 1) phases.push_back(s);
+    }
+    if (op != SGH_OP_HIERARCHIZE) std::reverse(phases.begin(), phases.end());
+    steps->insert(steps->end(), phases.begin(), phases.end());
+}
+
 std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o) {
     std::vector<Step> steps;
     if (g.d == 0) return steps;
@@ -506,19 +548,8 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
         choose_tile_tune(s.tile.chunk, &s.ttune);
         steps.push_back(s);
     } else {
-        // axis 0 too long for a tile: per-level fallback
-        for (int lev = 2; lev <= g.L[0]; ++lev) {
-            Step s;
-            s.kind = Step::LEVEL;
-            s.axes = {0};
-            s.key = 0;
-            s.level.data = g.data;
-            s.level.S = 1;
-            s.level.outer = g.N / g.n[0];
-            s.level.L = g.L[0];
-            s.level.lev = lev;
-            steps.push_back(s);
-        }
+        // axis 0 too long for a tile: dyadic block split
+        split_steps(op, g, 0, &steps);
         m = 1;
     }
     for (int k = m; k < g.d; ++k) {
@@ -577,23 +608,12 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
             s.ptune.nt = nt;
             steps.push_back(s);
         } else {
-            for (int lev = 2; lev <= L; ++lev) {
-                Step s;
-                s.kind = Step::LEVEL;
-                s.axes = {k};
-                s.key = k;
-                s.level.data = g.data;
-                s.level.S = g.st[k];
-                s.level.outer = g.N / (g.n[k] * g.st[k]);
-                s.level.L = L;
-                s.level.lev = lev;
-                steps.push_back(s);
-            }
+            split_steps(op, g, k, &steps);
         }
     }
     if (op != SGH_OP_HIERARCHIZE) {
-        // Inverse and transpose: launches in reverse axis order; the per-level
-        // launches of one long pole keep their coarse-to-fine order.
+        // Inverse and transpose: launches in reverse axis order; the split
+        // phases of one long pole keep their coarse-to-fine order.
         std::stable_sort(steps.begin(), steps.end(), [](const Step &a, const Step &b) { return a.key > b.key; });
     } else {
         // hierarchization of a long pole runs its levels fine to coarse
@@ -628,6 +648,7 @@ void retarget(std::vector<Step> &steps, void *data) {
         s.pole.data = data;
         s.level.data = data;
         s.tw.data = data;
+        s.split.data = data;
     }
 }
 
@@ -636,6 +657,7 @@ const char *step_name(const Step &s) {
         case Step::TILE: return "tile";
         case Step::POLE: return "pole";
         case Step::TW: return "tw";
+        case Step::SPLIT: return "split";
         default: return "level";
     }
 }
@@ -647,6 +669,7 @@ std::string step_timer_name(int op, int dtype, const Step &s) {
     if (s.kind == Step::POLE) ss << "_L" << s.pole.L;
     if (s.kind == Step::TILE) ss << "_m" << s.tile.g.m;
     if (s.kind == Step::TW) ss << "_m" << s.tw.g.m << "_L" << s.tw.L;
+    if (s.kind == Step::SPLIT) ss << "_L" << s.split.L << "_E" << s.split.E;
     return ss.str();
 }
 
@@ -657,6 +680,7 @@ hipError_t run_step(int op, int dtype, const Step &s, hipStream_t st) {
         case Step::TILE: return launch_tile(op, dtype, s.tile, s.ttune, st);
         case Step::POLE: return launch_pole(op, dtype, s.pole, s.ptune, st);
         case Step::TW: return launch_tw(op, dtype, s.tw, st);
+        case Step::SPLIT: return launch_split(op, dtype, s.split, st);
         default: return launch_level(op, dtype, s.level, st);
     }
 }
@@ -677,11 +701,14 @@ std::string describe_steps(int op, const Geom &g, const std::vector<Step> &steps
             ss << ",\"L\":" << s.pole.L << ",\"B\":" << s.pole.B << ",\"split\":" << s.pole.split << ",\"TB\":" << s.pole.TB
                << ",\"prefetch\":" << s.pole.pf << ",\"nt\":" << s.ptune.nt;
         if (s.kind == Step::LEVEL) ss << ",\"L\":" << s.level.L << ",\"lev\":" << s.level.lev;
+        if (s.kind == Step::SPLIT)
+            ss << ",\"L\":" << s.split.L << ",\"E\":" << s.split.E << ",\"Bs\":" << s.split.Bs << ",\"W\":" << s.split.W;
         if (s.kind == Step::TW)
             ss << ",\"L\":" << s.tw.L << ",\"B\":" << s.tw.B << ",\"split\":" << s.tw.split << ",\"TB\":" << s.tw.TB
                << ",\"ept\":" << s.tw.ept << ",\"tile\":" << s.tw.Sm << ",\"workgroups\":" << s.tw.nwg;
         ss << "}";
-        trips += (s.kind == Step::LEVEL) ? 0 : 1;
+        // per-level launches and the coarse split phases touch a small part of the grid
+        trips += (s.kind == Step::LEVEL || (s.kind == Step::SPLIT && s.split.E > 0)) ? 0 : 1;
     }
     ss << "],\"hbm_round_trips\":" << trips << "}";
     return ss.str();
@@ -1304,6 +1331,16 @@ int sgh_set_walk_preference(int32_t pref) {
     if (pref < 0 || pref > 1) return fail(SGH_ERR_ARG, "walk preference %d outside 0..1", pref);
     std::lock_guard<std::mutex> lk(g_override_mu);
     g_walk_pref = pref;
+    return SGH_OK;
+}
+
+int sgh_set_split_spans(int32_t fine, int32_t coarse) {
+    using namespace sgh;
+    if (fine < 0 || fine > 16 || coarse < 0 || coarse > 16)
+        return fail(SGH_ERR_ARG, "split span exponents %d, %d outside 0..16", fine, coarse);
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    g_split_fine = fine;
+    g_split_coarse = coarse;
     return SGH_OK;
 }
 

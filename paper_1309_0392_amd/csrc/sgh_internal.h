@@ -87,6 +87,34 @@ struct LevelLaunch {
     int32_t lev;
 };
 
+// One phase of the dyadic split of poles too long for one pass.  The pole
+// positions p = t * 2^E (t = 1 .. 2^(L-E) - 1, the "lattice" of this phase)
+// are cut into blocks of 2^Bs lattice steps; a workgroup loads one block of
+// W adjacent poles together with the two block-boundary positions (zero at
+// t = 0 and t = 2^(L-E)) and applies the 1-D rule for the levels inside the
+// block, which only involve the block and its boundaries.  The boundaries
+// are the next phase's lattice (E + Bs).  Hierarchization runs the phases
+// fine to coarse, the inverse and the transpose coarse to fine; the transpose
+// also takes, for each interior point of a phase with E > 0, its children
+// finer than the lattice (distances 2^(E-1) .. 1).
+struct SplitLaunch {
+    void *data;
+    int64_t S;      // elements between consecutive positions of a pole
+    int64_t outer;  // pole groups of S adjacent poles; group o starts at o * (2^L - 1) * S
+    int32_t L;      // pole level
+    int32_t E;      // lattice exponent
+    int32_t Bs;     // block span exponent along the lattice
+    int32_t W;      // adjacent poles per workgroup, a power of two <= 64
+};
+
+// Largest block span exponent of a split phase with W poles per workgroup
+// (the tile of W * (2^Bs + 1) elements stays within 64 KiB plus one row).
+inline int split_max_span(int W, int esize) {
+    int b = 1;
+    while (static_cast<int64_t>(W) * esize << (b + 1) <= 65536) ++b;
+    return b;
+}
+
 struct TileTune {
     int nt = 256;   // threads per workgroup
     int ept = 4;    // elements per thread (chunk <= nt * ept)
@@ -111,6 +139,7 @@ struct BatchTune {
     hipError_t launch_pole_##SUF(const PoleLaunch &p, const PoleTune &t, hipStream_t s);              \
     hipError_t launch_level_##SUF(const LevelLaunch &p, hipStream_t s);                              \
     hipError_t launch_tw_##SUF(const TWLaunch &p, hipStream_t s);                                     \
+    hipError_t launch_split_##SUF(const SplitLaunch &p, hipStream_t s);                               \
     hipError_t launch_batch_##SUF(const BatchTask *dev_tasks, int32_t ntasks, const BatchTune &t,    \
                                   hipStream_t s);
 SGH_DECLARE_LAUNCHERS(f64_h)
@@ -145,6 +174,9 @@ inline hipError_t launch_level(int op, int dtype, const LevelLaunch &p, hipStrea
     SGH_ROUTE(launch_level, p, s);
 }
 inline hipError_t launch_tw(int op, int dtype, const TWLaunch &p, hipStream_t s) { SGH_ROUTE(launch_tw, p, s); }
+inline hipError_t launch_split(int op, int dtype, const SplitLaunch &p, hipStream_t s) {
+    SGH_ROUTE(launch_split, p, s);
+}
 inline hipError_t launch_batch(int op, int dtype, const BatchTask *dev_tasks, int32_t ntasks, const BatchTune &t,
                                hipStream_t s) {
     SGH_ROUTE(launch_batch, dev_tasks, ntasks, t, s);

@@ -80,6 +80,7 @@ def lib():
             "sgh_set_fusion": ([i32], ctypes.c_int),
             "sgh_set_pole_split": ([i32, i32, i32, i32], ctypes.c_int),
             "sgh_set_walk_preference": ([i32], ctypes.c_int),
+            "sgh_set_split_spans": ([i32, i32], ctypes.c_int),
             "sgh_timing_reset": ([], ctypes.c_int),
             "sgh_timing_report": ([ctypes.c_char_p, i32], ctypes.c_int),
             "sgh_combi_create": ([ctypes.POINTER(vp), G, i32, ctypes.POINTER(ctypes.c_double), u32],
@@ -370,6 +371,11 @@ def set_fusion(level: int):
     """1 (default): fuse the LDS-tile axes with one register-walked strided axis; 2: fused, two-level
     walk only; 0: one launch per pass."""
     _check(lib().sgh_set_fusion(int(level)), "sgh_set_fusion")
+
+
+def set_split_spans(fine: int = 0, coarse: int = 0):
+    """Block span exponents of the dyadic split of long poles (0 = default)."""
+    _check(lib().sgh_set_split_spans(int(fine), int(coarse)), "sgh_set_split_spans")
 
 
 def set_walk_preference(pref: int):

@@ -111,16 +111,41 @@ def test_schedules():
     assert [(l["kind"], tuple(l["axes"])) for l in small["launches"]] == [("tile", (0, 1))]
     # level-1 axes are the identity and are dropped
     assert sgh.schedule(sgh.OP_HIERARCHIZE, (1, 1))["launches"] == []
-    # long poles use the per-level fallback: contiguous l=14 needs 13 levels
+    # long poles use the dyadic split: a contiguous l=14 pole is 4 blocks of
+    # 2^12 positions (FP64: 32 KiB tiles), then the level-2 lattice of the
+    # block boundaries
     lv = sgh.schedule(sgh.OP_HIERARCHIZE, (14,))["launches"]
-    assert [l["kind"] for l in lv] == ["level"] * 13
-    assert [l["lev"] for l in lv] == list(range(14, 1, -1))
-    lv = sgh.schedule(sgh.OP_ADJOINT, (3, 12))["launches"]
-    assert lv[0]["kind"] == "level" and [l["lev"] for l in lv[:11]] == list(range(2, 13))
-    assert lv[-1]["kind"] == "tile"
+    assert [(l["kind"], l["E"], l["Bs"], l["W"]) for l in lv] == [("split", 0, 12, 1), ("split", 12, 2, 1)]
+    lv = sgh.schedule(sgh.OP_ADJOINT, (14,))["launches"]
+    assert [(l["E"], l["Bs"]) for l in lv] == [(12, 2), (0, 12)]
+    # l=27 (1 GiB FP64): fine blocks of 2^12, then the level-15 coarse pole in
+    # blocks of 2^7 lattice steps, then the level-8 lattice, then the root
+    # (which only the transpose changes)
+    for op, order in ((sgh.OP_HIERARCHIZE, [0, 12, 19]), (sgh.OP_DEHIERARCHIZE, [19, 12, 0]),
+                      (sgh.OP_ADJOINT, [26, 19, 12, 0])):
+        lv = sgh.schedule(op, (27,))["launches"]
+        assert [l["E"] for l in lv] == order
+    # FP32 tiles hold twice the positions
+    lv = sgh.schedule(sgh.OP_HIERARCHIZE, (27,), sgh.F32)["launches"]
+    assert [(l["E"], l["Bs"]) for l in lv] == [(0, 13), (13, 7), (20, 7)]
+    try:
+        sgh.set_split_spans(12, 8)
+        lv = sgh.schedule(sgh.OP_HIERARCHIZE, (27,))["launches"]
+        assert [(l["E"], l["Bs"]) for l in lv] == [(0, 12), (12, 8), (20, 7)]
+        sgh.set_split_spans(16, 0)  # capped to what fits the tile
+        assert sgh.schedule(sgh.OP_HIERARCHIZE, (27,))["launches"][0]["Bs"] == 13
+    finally:
+        sgh.set_split_spans(0, 0)
+    with pytest.raises(sgh.SghError):
+        sgh.set_split_spans(-1, 0)
+    # a strided long axis: 32 adjacent poles per workgroup (stride 31), blocks of 2^7
+    lv = sgh.schedule(sgh.OP_ADJOINT, (5, 12))["launches"]
+    assert [(l["kind"], l.get("E"), l.get("Bs"), l.get("W")) for l in lv] == [
+        ("split", 7, 5, 32), ("split", 0, 7, 32), ("tile", None, None, None)]
     # a walked axis that is not the last one (the last is too long for registers)
     lv = sgh.schedule(sgh.OP_HIERARCHIZE, (10, 4, 11))["launches"]
-    assert [(l["kind"], tuple(l["axes"])) for l in lv] == [("tw", (0, 1))] + [("level", (2,))] * 10
+    assert [(l["kind"], tuple(l["axes"])) for l in lv] == [("tw", (0, 1)), ("split", (2,)), ("split", (2,))]
+    assert sgh.schedule(sgh.OP_HIERARCHIZE, (10, 4, 11))["hbm_round_trips"] == 2
     lv = sgh.schedule(sgh.OP_HIERARCHIZE, (10, 11, 4))["launches"]
     assert [(l["kind"], tuple(l["axes"])) for l in lv][0] == ("tw", (0, 2))
 
