@@ -231,6 +231,15 @@ int sgh_set_pole_split(int32_t level, int32_t top_exponent, int32_t block_expone
  * plans built after the call. */
 int sgh_set_split_spans(int32_t fine, int32_t coarse);
 
+/* Tuning knob for runs of consecutive small strided axes, which one launch
+ * transforms together: each workgroup loads W adjacent columns times the full
+ * extent of those axes into LDS (axes commute, Algorithm 1's outer loop may
+ * take them in any grouping).  A run is formed only while the box stays within
+ * `max_bytes` with rows (W elements) of at least `min_row_bytes`; 0 restores a
+ * default (64 KiB boxes, 128-byte rows).  Applies to schedules and plans
+ * built after the call; fusion level 0 forms no boxes. */
+int sgh_set_box_limits(int32_t max_bytes, int32_t min_row_bytes);
+
 /* Schedule switch: level 1 (default) fuses the leading LDS-tile axes with one
  * strided axis walked in registers into a single launch (one HBM round trip
  * for both); level 2 does the same but keeps the walk two-level; level 0 keeps

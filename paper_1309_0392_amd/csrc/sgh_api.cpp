@@ -268,7 +268,7 @@ void timing_drain_locked() {
 // ---------------------------------------------------------------------------
 // Schedule of one grid: a list of launches, applied in order.
 struct Step {
-    enum Kind { TILE, POLE, LEVEL, TW, SPLIT } kind = TILE;
+    enum Kind { TILE, POLE, LEVEL, TW, SPLIT, BOX } kind = TILE;
     TileLaunch tile{};
     TileTune ttune{};
     PoleLaunch pole{};
@@ -276,6 +276,7 @@ struct Step {
     LevelLaunch level{};
     TWLaunch tw{};
     SplitLaunch split{};
+    BoxLaunch box{};
     std::vector<int> axes;  // axes (of the reduced geometry) this launch transforms
     int key = 0;            // largest axis covered; orders the inverse/transpose schedule
 };
@@ -288,6 +289,8 @@ int g_pole3_override[SGH_MAX_LEVEL + 1] = {};  // 1 + TB * 100 + B * 10 + pf, 0 
 int g_fusion = 1;
 int g_walk_pref = 0;  // 0: smallest-stride walk candidate, 1: largest
 int g_split_fine = 0;    // block span exponent of the first split phase, 0 = largest that fits
+int g_box_bytes = 0;     // largest box launch tile in bytes, 0 = default
+int g_box_row = 0;       // smallest box row (columns * element size) in bytes, 0 = default
 int g_split_coarse = 0;  // the same for the later phases, 0 = default
 
 int pole_B_override(int L) {
@@ -448,6 +451,28 @@ std::vector<int> walk_candidates(const Geom &g) {
     return c;
 }
 
+// Columns per box-launch workgroup for a group of P points: the widest of
+// 64, 32, 16 adjacent columns whose box fits `bytes` with rows of at least
+// `row` bytes, or 0.
+struct BoxLimits {
+    int64_t bytes = 65536;
+    int row = 128;
+};
+
+BoxLimits box_limits() {
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    BoxLimits b;
+    if (g_box_bytes > 0) b.bytes = g_box_bytes;
+    if (g_box_row > 0) b.row = g_box_row;
+    return b;
+}
+
+int box_width(int64_t P, int esize, const BoxLimits &lim) {
+    for (int W : {64, 32, 16})
+        if (P * W * esize <= lim.bytes && W * esize >= lim.row) return W;
+    return 0;
+}
+
 // Launches of the dyadic split of axis k: phases with lattice exponents
 // E = 0, B0, B0 + B1, ... until the whole remaining pole fits one block;
 // fine to coarse for the hierarchization, coarse to fine otherwise.
@@ -554,6 +579,44 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
     }
     for (int k = m; k < g.d; ++k) {
         if (k == walk) continue;
+        if (fusion_level() >= 1) {
+            // consecutive small strided axes: one box launch for all of them
+            const BoxLimits lim = box_limits();
+            const int es = g.dtype == SGH_F64 ? 8 : 4;
+            int kend = k, W = box_width(g.n[k], es, lim);
+            int64_t P = g.n[k];
+            while (kend + 1 < g.d && kend + 1 != walk && box_width(P * g.n[kend + 1], es, lim) > 0) {
+                P *= g.n[++kend];
+                W = box_width(P, es, lim);
+            }
+            if (kend > k) {
+                Step s;
+                s.kind = Step::BOX;
+                for (int a = k; a <= kend; ++a) s.axes.push_back(a);
+                s.key = kend;
+                s.box.data = g.data;
+                s.box.S = g.st[k];
+                s.box.P = static_cast<int32_t>(P);
+                s.box.W = W;
+                s.box.outer = g.N / (g.st[k] * P);
+                TileGeom &tg = s.box.g;
+                tg.m = kend - k + 1;
+                int64_t st = W;
+                for (int a = 0; a < tg.m; ++a) {
+                    tg.L[a] = g.L[k + a];
+                    tg.n[a] = static_cast<int32_t>(g.n[k + a]);
+                    tg.st[a] = static_cast<int32_t>(st);
+                    tg.rst[a] = 1.0f / static_cast<float>(st);
+                    tg.rn[a] = 1.0f / static_cast<float>(g.n[k + a]);
+                    st *= g.n[k + a];
+                }
+                choose_tile_tune(P * W, &s.ttune);
+                if (s.ttune.ept < 4) s.ttune.ept = 4;
+                steps.push_back(s);
+                k = kend;
+                continue;
+            }
+        }
         const int L = g.L[k];
         int B = default_pole_B(L);
         int nt = 256;
@@ -649,6 +712,7 @@ void retarget(std::vector<Step> &steps, void *data) {
         s.level.data = data;
         s.tw.data = data;
         s.split.data = data;
+        s.box.data = data;
     }
 }
 
@@ -658,6 +722,7 @@ const char *step_name(const Step &s) {
         case Step::POLE: return "pole";
         case Step::TW: return "tw";
         case Step::SPLIT: return "split";
+        case Step::BOX: return "box";
         default: return "level";
     }
 }
@@ -670,6 +735,7 @@ std::string step_timer_name(int op, int dtype, const Step &s) {
     if (s.kind == Step::TILE) ss << "_m" << s.tile.g.m;
     if (s.kind == Step::TW) ss << "_m" << s.tw.g.m << "_L" << s.tw.L;
     if (s.kind == Step::SPLIT) ss << "_L" << s.split.L << "_E" << s.split.E;
+    if (s.kind == Step::BOX) ss << "_m" << s.box.g.m;
     return ss.str();
 }
 
@@ -681,6 +747,7 @@ hipError_t run_step(int op, int dtype, const Step &s, hipStream_t st) {
         case Step::POLE: return launch_pole(op, dtype, s.pole, s.ptune, st);
         case Step::TW: return launch_tw(op, dtype, s.tw, st);
         case Step::SPLIT: return launch_split(op, dtype, s.split, st);
+        case Step::BOX: return launch_box(op, dtype, s.box, s.ttune, st);
         default: return launch_level(op, dtype, s.level, st);
     }
 }
@@ -703,6 +770,9 @@ std::string describe_steps(int op, const Geom &g, const std::vector<Step> &steps
         if (s.kind == Step::LEVEL) ss << ",\"L\":" << s.level.L << ",\"lev\":" << s.level.lev;
         if (s.kind == Step::SPLIT)
             ss << ",\"L\":" << s.split.L << ",\"E\":" << s.split.E << ",\"Bs\":" << s.split.Bs << ",\"W\":" << s.split.W;
+        if (s.kind == Step::BOX)
+            ss << ",\"W\":" << s.box.W << ",\"box\":" << s.box.P * s.box.W << ",\"nt\":" << s.ttune.nt
+               << ",\"ept\":" << s.ttune.ept;
         if (s.kind == Step::TW)
             ss << ",\"L\":" << s.tw.L << ",\"B\":" << s.tw.B << ",\"split\":" << s.tw.split << ",\"TB\":" << s.tw.TB
                << ",\"ept\":" << s.tw.ept << ",\"tile\":" << s.tw.Sm << ",\"workgroups\":" << s.tw.nwg;
@@ -1341,6 +1411,16 @@ int sgh_set_split_spans(int32_t fine, int32_t coarse) {
     std::lock_guard<std::mutex> lk(g_override_mu);
     g_split_fine = fine;
     g_split_coarse = coarse;
+    return SGH_OK;
+}
+
+int sgh_set_box_limits(int32_t max_bytes, int32_t min_row_bytes) {
+    using namespace sgh;
+    if (max_bytes < 0 || max_bytes > 160 * 1024 || min_row_bytes < 0 || min_row_bytes > 512)
+        return fail(SGH_ERR_ARG, "box limits %d, %d outside 0..%d, 0..512", max_bytes, min_row_bytes, 160 * 1024);
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    g_box_bytes = max_bytes;
+    g_box_row = min_row_bytes;
     return SGH_OK;
 }
 

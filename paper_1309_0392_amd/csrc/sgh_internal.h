@@ -87,6 +87,20 @@ struct LevelLaunch {
     int32_t lev;
 };
 
+// Several consecutive small strided axes in one pass.  A workgroup loads a
+// box of W adjacent columns (consecutive elements below the stride S of the
+// group's first axis) times the full extent of the group's axes (P points)
+// into LDS, transforms the group's axes there with the tile code (the W
+// columns are a batch dimension) and writes the box back.
+struct BoxLaunch {
+    void *data;
+    int64_t S;      // stride of the group's first axis
+    int64_t outer;  // total / (S * P)
+    int32_t P;      // product of the group's n_k
+    int32_t W;      // columns per workgroup, a power of two
+    TileGeom g;     // the group's axes inside the box (strides W * prod of earlier n)
+};
+
 // One phase of the dyadic split of poles too long for one pass.  The pole
 // positions p = t * 2^E (t = 1 .. 2^(L-E) - 1, the "lattice" of this phase)
 // are cut into blocks of 2^Bs lattice steps; a workgroup loads one block of
@@ -140,6 +154,7 @@ struct BatchTune {
     hipError_t launch_level_##SUF(const LevelLaunch &p, hipStream_t s);                              \
     hipError_t launch_tw_##SUF(const TWLaunch &p, hipStream_t s);                                     \
     hipError_t launch_split_##SUF(const SplitLaunch &p, hipStream_t s);                               \
+    hipError_t launch_box_##SUF(const BoxLaunch &p, const TileTune &t, hipStream_t s);                \
     hipError_t launch_batch_##SUF(const BatchTask *dev_tasks, int32_t ntasks, const BatchTune &t,    \
                                   hipStream_t s);
 SGH_DECLARE_LAUNCHERS(f64_h)
@@ -176,6 +191,9 @@ inline hipError_t launch_level(int op, int dtype, const LevelLaunch &p, hipStrea
 inline hipError_t launch_tw(int op, int dtype, const TWLaunch &p, hipStream_t s) { SGH_ROUTE(launch_tw, p, s); }
 inline hipError_t launch_split(int op, int dtype, const SplitLaunch &p, hipStream_t s) {
     SGH_ROUTE(launch_split, p, s);
+}
+inline hipError_t launch_box(int op, int dtype, const BoxLaunch &p, const TileTune &t, hipStream_t s) {
+    SGH_ROUTE(launch_box, p, t, s);
 }
 inline hipError_t launch_batch(int op, int dtype, const BatchTask *dev_tasks, int32_t ntasks, const BatchTune &t,
                                hipStream_t s) {

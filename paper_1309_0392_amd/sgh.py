@@ -81,6 +81,7 @@ def lib():
             "sgh_set_pole_split": ([i32, i32, i32, i32], ctypes.c_int),
             "sgh_set_walk_preference": ([i32], ctypes.c_int),
             "sgh_set_split_spans": ([i32, i32], ctypes.c_int),
+            "sgh_set_box_limits": ([i32, i32], ctypes.c_int),
             "sgh_timing_reset": ([], ctypes.c_int),
             "sgh_timing_report": ([ctypes.c_char_p, i32], ctypes.c_int),
             "sgh_combi_create": ([ctypes.POINTER(vp), G, i32, ctypes.POINTER(ctypes.c_double), u32],
@@ -376,6 +377,11 @@ def set_fusion(level: int):
 def set_split_spans(fine: int = 0, coarse: int = 0):
     """Block span exponents of the dyadic split of long poles (0 = default)."""
     _check(lib().sgh_set_split_spans(int(fine), int(coarse)), "sgh_set_split_spans")
+
+
+def set_box_limits(max_bytes: int = 0, min_row_bytes: int = 0):
+    """Size limits of the launches that transform runs of small strided axes together (0 = default)."""
+    _check(lib().sgh_set_box_limits(int(max_bytes), int(min_row_bytes)), "sgh_set_box_limits")
 
 
 def set_walk_preference(pref: int):

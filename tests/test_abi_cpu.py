@@ -150,6 +150,37 @@ def test_schedules():
     assert [(l["kind"], tuple(l["axes"])) for l in lv][0] == ("tw", (0, 2))
 
 
+def test_box_schedules():
+    # the 10-dimensional anisotropic shape: the first axis refined, nine axes of 3 points
+    ten = (12,) + (2,) * 9
+    s = sgh.schedule(sgh.OP_HIERARCHIZE, ten)
+    assert [(l["kind"], tuple(l["axes"])) for l in s["launches"]] == [
+        ("tw", (0, 1)), ("box", (2, 3, 4, 5, 6)), ("box", (7, 8, 9))]
+    assert [l.get("W") for l in s["launches"]] == [None, 32, 64] and s["hbm_round_trips"] == 3
+    d = sgh.schedule(sgh.OP_DEHIERARCHIZE, ten)
+    assert [tuple(l["axes"]) for l in d["launches"]] == [(7, 8, 9), (2, 3, 4, 5, 6), (0, 1)]
+    # boxes stay within the limits; a single small axis keeps its pole launch
+    try:
+        sgh.set_box_limits(16384, 256)
+        s = sgh.schedule(sgh.OP_HIERARCHIZE, ten)
+        assert [len(l["axes"]) for l in s["launches"]] == [2, 3, 3, 2]
+        assert all(l["box"] * 8 <= 16384 and l["W"] * 8 >= 256 for l in s["launches"] if l["kind"] == "box")
+    finally:
+        sgh.set_box_limits(0, 0)
+    assert [l["kind"] for l in sgh.schedule(sgh.OP_HIERARCHIZE, (10, 9, 8))["launches"]] == ["tw", "pole"]
+    # FP32 rows of 16 columns are too short to pair the two level-5 axes of (6,6,5,5,5)
+    s = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_5D, sgh.F32)
+    assert [l["kind"] for l in s["launches"]] == ["tw", "pole", "pole"]
+    # fusion level 0: one launch per strided axis
+    try:
+        sgh.set_fusion(0)
+        assert "box" not in [l["kind"] for l in sgh.schedule(sgh.OP_HIERARCHIZE, ten)["launches"]]
+    finally:
+        sgh.set_fusion(1)
+    with pytest.raises(sgh.SghError):
+        sgh.set_box_limits(-1, 0)
+
+
 def test_fusion_switch():
     try:
         sgh.set_fusion(0)
