@@ -1,7 +1,7 @@
 """Benchmark: grid points hierarchized per second on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f64|f32]
-                    [--no-cpu-baseline] [--no-extras]
+                    [--no-cpu-baseline] [--no-extras] [--workload NAME]
 
 One step is one in-place hierarchization (all axes) of the d=3 anisotropic
 grid of level (10, 9, 8): 1023 x 511 x 255 = 133,302,015 points, 1.07 GB in
@@ -9,6 +9,13 @@ FP64, values prod_k sin(pi x_k) + 0.01 N(0,1) (seed 1), already resident in
 HBM.  The step is timed with HIP events on the launch stream; every library
 kernel is also bracketed by its own events (sgh_timing_*), which gives the
 per-kernel durations behind the roofline figure.
+
+With --workload NAME it times one secondary workload instead and prints its
+own JSON line (value, roofline of its dominant kernel, CPU oracle sample):
+pole27 (one pole of level 27, 1.07 GB FP64), tend12 (the 10-dimensional
+shape (12,2,...,2), 645 MB FP64), combi_d4n15 (gather / scatter between the
+d=4, n=15 combination set and its sparse grid, 1.1 GB FP64), batch (the
+d=4, n=10 set as one plan) and batch128 (128 copies of that set, 1.0 GB).
 
 Prints one JSON line.  `value` is points/s of the whole job (one GPU).
 Extra fields: the inverse and the transpose on the same grid, the batched
@@ -46,6 +53,9 @@ def parse():
                     help="autotune the schedule of the grid first (timed trial launches on scratch grids)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only copy a buffer of the workload's size (reference kernel for HBM counters)")
+    ap.add_argument("--workload", choices=["aniso3d"] + sorted(SECONDARY), default="aniso3d",
+                    help="aniso3d (default): the benchmark grid; the others time one secondary workload "
+                         "(its own JSON line, roofline of its dominant kernel)")
     return ap.parse_args()
 
 
@@ -87,6 +97,133 @@ def time_region(torch, fn, steps):
     return a.elapsed_time(b)
 
 
+# ----------------------------------------------------------- secondary workloads
+def timed_kernels(torch, sgh, fn, steps):
+    """ms per call of fn over `steps` calls, and the library's per-kernel report."""
+    fn()
+    torch.cuda.synchronize()
+    sgh.timing_reset()
+    sgh.timing_enable(True)
+    ms = time_region(torch, fn, steps) / steps
+    report = sgh.timing_report()
+    sgh.timing_enable(False)
+    return ms, report
+
+
+def roofline_of(report, bytes_per_launch, dominant=None):
+    """Roofline entry for the kernel with the largest share of the timed region
+    (or the named one); bytes_per_launch maps kernel name -> algorithmic bytes."""
+    name = dominant or max(report.items(), key=lambda kv: kv[1]["ms"])[0]
+    st = report[name]
+    avg = st["ms"] / st["count"]
+    algo = bytes_per_launch(name)
+    ach = algo / (avg * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(name), "algorithmic_bytes_per_launch": algo,
+            "avg_launch_ms": avg}
+
+
+def kernel_table(report):
+    return {k: {"launches": v["count"], "avg_ms": v["ms"] / v["count"]} for k, v in report.items()}
+
+
+def secondary_grid(args, torch, np, sgh, W, name):
+    """One large grid: the level-27 pole or the 10-dimensional shape (FP64)."""
+    if name == "pole27":
+        levels, desc = (27,), "one pole of level 27: 134,217,727 points, 1.07 GB FP64"
+    else:
+        levels, desc = (12,) + (2,) * 9, "10-d (12,2,2,2,2,2,2,2,2,2): 4095 x 3^9 = 80,601,885 points, 645 MB FP64"
+    x_host = W.sine_plus_noise(levels, seed=8) if name == "pole27" else W.uniform(levels, 9)
+    x = torch.from_numpy(x_host).cuda()
+    N = x.numel()
+    out = {"metric": "grid points hierarchized/s (%s)" % name, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": desc, "levels": list(levels), "points": N}}
+    for _ in range(args.warmup):
+        sgh.hierarchize(x, levels)
+    ms, rep = timed_kernels(torch, sgh, lambda: sgh.hierarchize(x, levels), args.steps)
+    out.update({"value": N / (ms * 1e-3), "ms_per_step": ms, "kernels": kernel_table(rep),
+                "schedule": sgh.schedule(sgh.OP_HIERARCHIZE, levels)["launches"],
+                "roofline": roofline_of(rep, lambda k: 2.0 * N * 8)})
+    extras = {}
+    for nm, op in (("dehierarchize", sgh.OP_DEHIERARCHIZE), ("adjoint", sgh.OP_ADJOINT)):
+        ms_o, rep_o = timed_kernels(torch, sgh, lambda op=op: sgh.transform(op, x, levels), args.steps)
+        extras[nm] = {"points_per_s": N / (ms_o * 1e-3), "ms": ms_o, "kernels": kernel_table(rep_o)}
+    out["extras"] = extras
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.time()
+        oracle.hierarchize(x_host, levels)
+        sec = time.time() - t
+        out["cpu_baseline"] = {"value": N / sec, "unit": "points/s", "cores": 1, "kind": "oracle",
+                               "sample": "the whole grid, FP64, hierarchized once by the C oracle (one thread)"}
+    return out
+
+
+def secondary_combination(args, torch, np, sgh, W, name):
+    """Sparse grid of the d=4, n=15 combination set: gather and scatter (FP64)."""
+    lv, co = W.combination_set(4, 15)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(10)
+    xs = [torch.rand(W.shape_of(l), dtype=torch.float64, device="cuda", generator=gen) for l in lv]
+    npts = sum(t.numel() for t in xs)
+    comb = sgh.Combination(xs, lv, co, graph=False)
+    sp = comb.new_sparse()
+    algo = (npts + comb.sparse_points) * 8.0
+    for _ in range(args.warmup):
+        comb.gather(sp)
+        comb.scatter(sp)
+    ms_g, rep_g = timed_kernels(torch, sgh, lambda: comb.gather(sp), args.steps)
+    ms_s, rep_s = timed_kernels(torch, sgh, lambda: comb.scatter(sp), args.steps)
+    out = {"metric": "grid points gathered into the sparse grid/s (d=4, n=15 combination set)", "unit": "points/s",
+           "value": npts / (ms_g * 1e-3), "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_g, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "sparse grid of the d=4, n=15 combination set: %d grids, %d grid points, "
+                                  "%d sparse points, FP64" % (len(lv), npts, comb.sparse_points)},
+           "roofline": roofline_of(rep_g, lambda k: algo),
+           "extras": {"scatter": {"points_per_s": npts / (ms_s * 1e-3), "ms": ms_s,
+                                  "roofline": roofline_of(rep_s, lambda k: algo)}}}
+    comb.close()
+    if not args.no_cpu_baseline:
+        import oracle
+        lv10, c10 = W.combination_set()
+        hs = W.combination_values(lv10, seed=3)
+        t = time.time()
+        oracle.combi_gather(hs, lv10, c10)
+        sec = time.time() - t
+        out["cpu_baseline"] = {"value": sum(h.size for h in hs) / sec, "unit": "points/s", "cores": 1, "kind": "oracle",
+                               "sample": "the oracle's gather on the d=4, n=10 set (980,797 grid points), once"}
+    return out
+
+
+def secondary_batch(args, torch, np, sgh, W, name):
+    """The d=4, n=10 combination set as one batched plan; `batch128` holds 128 copies
+    of the set (75,392 grids, 1.0 GB FP64) so that HBM, not latency, bounds it."""
+    lv, co = W.combination_set()
+    R = 128 if name == "batch128" else 1
+    xs = [torch.from_numpy(a).cuda() for _ in range(R) for a in W.combination_values(lv, seed=3)]
+    lvs = [l for _ in range(R) for l in lv]
+    npts = sum(t.numel() for t in xs)
+    plan = sgh.Plan(sgh.OP_HIERARCHIZE, xs, lvs, graph=True, autotune=True)
+    for _ in range(args.warmup):
+        plan.execute()
+    ms, rep = timed_kernels(torch, sgh, plan.execute, args.steps)
+    out = {"metric": "grid points hierarchized/s (batched combination set)", "unit": "points/s",
+           "value": npts / (ms * 1e-3), "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "%d copies of the d=4, n=10 combination set: %d grids, %d points, FP64"
+                                  % (R, len(lvs), npts)},
+           "kernels": kernel_table(rep), "plan": plan.describe()["batches"],
+           "roofline": roofline_of(rep, lambda k: 2.0 * npts * 8)}
+    plan.close()
+    return out
+
+
+SECONDARY = {"pole27": secondary_grid, "tend12": secondary_grid, "combi_d4n15": secondary_combination,
+             "batch": secondary_batch, "batch128": secondary_batch}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -104,6 +241,9 @@ def main():
     sgh.lib()  # fails loudly if the HIP library is not built
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload != "aniso3d":
+        print(json.dumps(SECONDARY[args.workload](args, torch, np, sgh, W, args.workload)))
+        return
     dt_np = np.float64 if args.dtype == "f64" else np.float32
     esize = 8 if args.dtype == "f64" else 4
     levels = W.ANISO_3D

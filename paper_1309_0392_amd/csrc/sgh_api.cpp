@@ -849,6 +849,9 @@ void batch_default_tune(const DevInfo &di, int maxN, int ntasks, int dtype, Batc
 }  // namespace
 
 int report_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
+LaunchTimer::LaunchTimer(const char *name, hipStream_t s) : impl_(new TimerScope(name, s)) {}
+LaunchTimer::~LaunchTimer() { delete static_cast<TimerScope *>(impl_); }
 }  // namespace sgh
 
 struct sgh_plan {

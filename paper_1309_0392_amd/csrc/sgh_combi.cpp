@@ -162,11 +162,13 @@ CombiLaunch launch_of(const sgh_combi &c, bool gather, void *sparse) {
 }
 
 hipError_t do_gather(const sgh_combi &c, void *sparse, hipStream_t s) {
+    LaunchTimer t(c.dtype == SGH_F64 ? "combi_f64_gather" : "combi_f32_gather", s);
     const CombiLaunch p = launch_of(c, true, sparse);
     return c.dtype == SGH_F64 ? launch_combi_gather_f64(p, s) : launch_combi_gather_f32(p, s);
 }
 
 hipError_t do_scatter(const sgh_combi &c, const void *sparse, hipStream_t s) {
+    LaunchTimer t(c.dtype == SGH_F64 ? "combi_f64_scatter" : "combi_f32_scatter", s);
     const CombiLaunch p = launch_of(c, false, const_cast<void *>(sparse));
     return c.dtype == SGH_F64 ? launch_combi_scatter_f64(p, s) : launch_combi_scatter_f32(p, s);
 }

@@ -265,6 +265,19 @@ struct CombiLaunch {
 // Records `msg` as the library's last error message; returns `code`.
 int report_error(int code, const char *msg);
 
+// Brackets the launches made on `s` during its lifetime with timing events
+// while sgh_timing_enable is on (reported under `name`).
+class LaunchTimer {
+public:
+    LaunchTimer(const char *name, hipStream_t s);
+    ~LaunchTimer();
+    LaunchTimer(const LaunchTimer &) = delete;
+    LaunchTimer &operator=(const LaunchTimer &) = delete;
+
+private:
+    void *impl_;
+};
+
 hipError_t launch_combi_gather_f64(const CombiLaunch &p, hipStream_t s);
 hipError_t launch_combi_gather_f32(const CombiLaunch &p, hipStream_t s);
 hipError_t launch_combi_scatter_f64(const CombiLaunch &p, hipStream_t s);
