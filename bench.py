@@ -69,9 +69,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if it
-    was taken with the current kernel sources (else None)."""
+def measured_traffic(kernel: str, workload: str = "aniso3d"):
+    """HBM bytes per launch of `kernel` in `workload` from the committed counter
+    summary, if it was taken with the current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         with open(path) as f:
@@ -80,7 +80,7 @@ def measured_traffic(kernel: str):
         return None
     if data.get("source_hash") != kernel_source_hash():
         return None
-    entry = data.get("kernels", {}).get(kernel)
+    entry = data.get("workloads", {}).get(workload, {}).get(kernel)
     return None if entry is None else entry.get("bytes_per_launch")
 
 
@@ -110,7 +110,7 @@ def timed_kernels(torch, sgh, fn, steps):
     return ms, report
 
 
-def roofline_of(report, bytes_per_launch, dominant=None):
+def roofline_of(report, bytes_per_launch, workload, dominant=None):
     """Roofline entry for the kernel with the largest share of the timed region
     (or the named one); bytes_per_launch maps kernel name -> algorithmic bytes."""
     name = dominant or max(report.items(), key=lambda kv: kv[1]["ms"])[0]
@@ -119,7 +119,7 @@ def roofline_of(report, bytes_per_launch, dominant=None):
     algo = bytes_per_launch(name)
     ach = algo / (avg * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(name), "algorithmic_bytes_per_launch": algo,
+            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(name, workload), "algorithmic_bytes_per_launch": algo,
             "avg_launch_ms": avg}
 
 
@@ -144,12 +144,13 @@ def secondary_grid(args, torch, np, sgh, W, name):
     ms, rep = timed_kernels(torch, sgh, lambda: sgh.hierarchize(x, levels), args.steps)
     out.update({"value": N / (ms * 1e-3), "ms_per_step": ms, "kernels": kernel_table(rep),
                 "schedule": sgh.schedule(sgh.OP_HIERARCHIZE, levels)["launches"],
-                "roofline": roofline_of(rep, lambda k: 2.0 * N * 8)})
-    extras = {}
-    for nm, op in (("dehierarchize", sgh.OP_DEHIERARCHIZE), ("adjoint", sgh.OP_ADJOINT)):
-        ms_o, rep_o = timed_kernels(torch, sgh, lambda op=op: sgh.transform(op, x, levels), args.steps)
-        extras[nm] = {"points_per_s": N / (ms_o * 1e-3), "ms": ms_o, "kernels": kernel_table(rep_o)}
-    out["extras"] = extras
+                "roofline": roofline_of(rep, lambda k: 2.0 * N * 8, name)})
+    if not args.no_extras:
+        extras = {}
+        for nm, op in (("dehierarchize", sgh.OP_DEHIERARCHIZE), ("adjoint", sgh.OP_ADJOINT)):
+            ms_o, rep_o = timed_kernels(torch, sgh, lambda op=op: sgh.transform(op, x, levels), args.steps)
+            extras[nm] = {"points_per_s": N / (ms_o * 1e-3), "ms": ms_o, "kernels": kernel_table(rep_o)}
+        out["extras"] = extras
     if not args.no_cpu_baseline:
         import oracle
         t = time.time()
@@ -181,9 +182,9 @@ def secondary_combination(args, torch, np, sgh, W, name):
            "data": "synthetic",
            "config": {"workload": "sparse grid of the d=4, n=15 combination set: %d grids, %d grid points, "
                                   "%d sparse points, FP64" % (len(lv), npts, comb.sparse_points)},
-           "roofline": roofline_of(rep_g, lambda k: algo),
+           "roofline": roofline_of(rep_g, lambda k: algo, name),
            "extras": {"scatter": {"points_per_s": npts / (ms_s * 1e-3), "ms": ms_s,
-                                  "roofline": roofline_of(rep_s, lambda k: algo)}}}
+                                  "roofline": roofline_of(rep_s, lambda k: algo, name)}}}
     comb.close()
     if not args.no_cpu_baseline:
         import oracle
@@ -215,7 +216,7 @@ def secondary_batch(args, torch, np, sgh, W, name):
            "config": {"workload": "%d copies of the d=4, n=10 combination set: %d grids, %d points, FP64"
                                   % (R, len(lvs), npts)},
            "kernels": kernel_table(rep), "plan": plan.describe()["batches"],
-           "roofline": roofline_of(rep, lambda k: 2.0 * npts * 8)}
+           "roofline": roofline_of(rep, lambda k: 2.0 * npts * 8, name)}
     plan.close()
     return out
 
