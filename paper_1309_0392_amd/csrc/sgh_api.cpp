@@ -268,12 +268,11 @@ void timing_drain_locked() {
 // ---------------------------------------------------------------------------
 // Schedule of one grid: a list of launches, applied in order.
 struct Step {
-    enum Kind { TILE, POLE, LEVEL, TW, SPLIT, BOX } kind = TILE;
+    enum Kind { TILE, POLE, TW, SPLIT, BOX } kind = TILE;
     TileLaunch tile{};
     TileTune ttune{};
     PoleLaunch pole{};
     PoleTune ptune{};
-    LevelLaunch level{};
     TWLaunch tw{};
     SplitLaunch split{};
     BoxLaunch box{};
@@ -678,21 +677,6 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
         // Inverse and transpose: launches in reverse axis order; the split
         // phases of one long pole keep their coarse-to-fine order.
         std::stable_sort(steps.begin(), steps.end(), [](const Step &a, const Step &b) { return a.key > b.key; });
-    } else {
-        // hierarchization of a long pole runs its levels fine to coarse
-        std::vector<Step> out;
-        size_t i = 0;
-        while (i < steps.size()) {
-            if (steps[i].kind != Step::LEVEL) {
-                out.push_back(steps[i++]);
-                continue;
-            }
-            size_t j = i;
-            while (j < steps.size() && steps[j].kind == Step::LEVEL && steps[j].key == steps[i].key) ++j;
-            for (size_t t = j; t > i; --t) out.push_back(steps[t - 1]);
-            i = j;
-        }
-        steps.swap(out);
     }
     return steps;
 }
@@ -709,7 +693,6 @@ void retarget(std::vector<Step> &steps, void *data) {
     for (auto &s : steps) {
         s.tile.data = data;
         s.pole.data = data;
-        s.level.data = data;
         s.tw.data = data;
         s.split.data = data;
         s.box.data = data;
@@ -722,8 +705,7 @@ const char *step_name(const Step &s) {
         case Step::POLE: return "pole";
         case Step::TW: return "tw";
         case Step::SPLIT: return "split";
-        case Step::BOX: return "box";
-        default: return "level";
+        default: return "box";
     }
 }
 
@@ -748,7 +730,7 @@ hipError_t run_step(int op, int dtype, const Step &s, hipStream_t st) {
         case Step::TW: return launch_tw(op, dtype, s.tw, st);
         case Step::SPLIT: return launch_split(op, dtype, s.split, st);
         case Step::BOX: return launch_box(op, dtype, s.box, s.ttune, st);
-        default: return launch_level(op, dtype, s.level, st);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -767,7 +749,6 @@ std::string describe_steps(int op, const Geom &g, const std::vector<Step> &steps
         if (s.kind == Step::POLE)
             ss << ",\"L\":" << s.pole.L << ",\"B\":" << s.pole.B << ",\"split\":" << s.pole.split << ",\"TB\":" << s.pole.TB
                << ",\"prefetch\":" << s.pole.pf << ",\"nt\":" << s.ptune.nt;
-        if (s.kind == Step::LEVEL) ss << ",\"L\":" << s.level.L << ",\"lev\":" << s.level.lev;
         if (s.kind == Step::SPLIT)
             ss << ",\"L\":" << s.split.L << ",\"E\":" << s.split.E << ",\"Bs\":" << s.split.Bs << ",\"W\":" << s.split.W;
         if (s.kind == Step::BOX)
@@ -777,8 +758,8 @@ std::string describe_steps(int op, const Geom &g, const std::vector<Step> &steps
             ss << ",\"L\":" << s.tw.L << ",\"B\":" << s.tw.B << ",\"split\":" << s.tw.split << ",\"TB\":" << s.tw.TB
                << ",\"ept\":" << s.tw.ept << ",\"tile\":" << s.tw.Sm << ",\"workgroups\":" << s.tw.nwg;
         ss << "}";
-        // per-level launches and the coarse split phases touch a small part of the grid
-        trips += (s.kind == Step::LEVEL || (s.kind == Step::SPLIT && s.split.E > 0)) ? 0 : 1;
+        // the coarse split phases touch a small part of the grid
+        trips += (s.kind == Step::SPLIT && s.split.E > 0) ? 0 : 1;
     }
     ss << "],\"hbm_round_trips\":" << trips << "}";
     return ss.str();

@@ -78,15 +78,6 @@ struct TWLaunch {
     TileGeom g;   // tile axes
 };
 
-// One level of the generic per-level fallback for long poles.
-struct LevelLaunch {
-    void *data;
-    int64_t outer;  // poles per S-run: total / (n * S)
-    int64_t S;
-    int32_t L;
-    int32_t lev;
-};
-
 // Several consecutive small strided axes in one pass.  A workgroup loads a
 // box of W adjacent columns (consecutive elements below the stride S of the
 // group's first axis) times the full extent of the group's axes (P points)
@@ -151,7 +142,6 @@ struct BatchTune {
 #define SGH_DECLARE_LAUNCHERS(SUF)                                                                    \
     hipError_t launch_tile_##SUF(const TileLaunch &p, const TileTune &t, hipStream_t s);              \
     hipError_t launch_pole_##SUF(const PoleLaunch &p, const PoleTune &t, hipStream_t s);              \
-    hipError_t launch_level_##SUF(const LevelLaunch &p, hipStream_t s);                              \
     hipError_t launch_tw_##SUF(const TWLaunch &p, hipStream_t s);                                     \
     hipError_t launch_split_##SUF(const SplitLaunch &p, hipStream_t s);                               \
     hipError_t launch_box_##SUF(const BoxLaunch &p, const TileTune &t, hipStream_t s);                \
@@ -184,9 +174,6 @@ inline hipError_t launch_tile(int op, int dtype, const TileLaunch &p, const Tile
 }
 inline hipError_t launch_pole(int op, int dtype, const PoleLaunch &p, const PoleTune &t, hipStream_t s) {
     SGH_ROUTE(launch_pole, p, t, s);
-}
-inline hipError_t launch_level(int op, int dtype, const LevelLaunch &p, hipStream_t s) {
-    SGH_ROUTE(launch_level, p, s);
 }
 inline hipError_t launch_tw(int op, int dtype, const TWLaunch &p, hipStream_t s) { SGH_ROUTE(launch_tw, p, s); }
 inline hipError_t launch_split(int op, int dtype, const SplitLaunch &p, hipStream_t s) {

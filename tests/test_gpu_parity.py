@@ -2,8 +2,8 @@
 
 Shapes are chosen so that each launch schedule of the library runs: whole grid
 in one LDS tile, LDS tile over the leading axes plus register-resident strided
-poles (every supported block split), the per-level fallback for long poles,
-level-1 axes, and up to 16 dimensions."""
+poles (every supported block split), the dyadic split of long poles, runs of
+small strided axes in one box launch, level-1 axes, and up to 16 dimensions."""
 import numpy as np
 import pytest
 import torch
@@ -23,7 +23,7 @@ SHAPES = [
     (1,), (2,), (5,), (13,), (5, 5), (3, 2, 4), (2, 2, 2, 2, 2, 2), (1, 3, 1, 2), (10, 3),
     # leading-axes tile + strided poles (FP64 tile capacity 8192 points)
     (7, 7), (10, 2), (10, 4, 3), (4, 4, 6), (3, 3, 3, 9), (5, 9), (2, 10, 2), (6, 8), (4, 10), (3, 5, 2, 5),
-    # per-level fallback: contiguous axis too long for a tile, strided axis too long for registers
+    # dyadic split: contiguous axis too long for a tile, strided axis too long for registers
     (14,), (3, 11), (2, 12, 2),
     # many dimensions, and the 10-d anisotropic stress shape (first axis grows, others 3 points)
     (2,) * 10, (6,) + (2,) * 9, (2, 2, 2, 2, 2, 2) + (1,) * 9 + (3,),
