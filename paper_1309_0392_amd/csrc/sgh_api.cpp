@@ -809,7 +809,8 @@ struct PlanLarge {
 
 int batch_lds_limit(int dtype) { return dtype == SGH_F64 ? 8192 * 8 : 16384 * 4; }
 
-void batch_default_tune(const DevInfo &di, int maxN, int ntasks, int dtype, BatchTune *t, int nt_pref = 0) {
+void batch_default_tune(const DevInfo &di, int maxN, int ntasks, int dtype, BatchTune *t, int nt_pref = 0,
+                        int persist = -1) {
     int nt = nt_pref ? nt_pref : 256;
     int ept = pow2_ceil((maxN + nt - 1) / nt);
     if (ept < 4) ept = 4;
@@ -821,10 +822,15 @@ void batch_default_tune(const DevInfo &di, int maxN, int ntasks, int dtype, Batc
     t->nt = nt;
     t->ept = ept;
     t->lds_bytes = std::max<int>(static_cast<int>(maxN * esize_of(dtype)), 16);
-    // one workgroup per grid: the dispatcher hands out grids as workgroups
-    // retire (largest first), which needs no shared queue counter
-    (void)di;
-    t->nwg = std::max(1, ntasks);
+    // resident workgroups per CU, bounded by LDS and by waves
+    const int by_lds = std::max(1, di.lds_per_cu / t->lds_bytes);
+    const int by_waves = std::max(1, 32 / (nt / 64));
+    const int resident = std::min({by_lds, by_waves, 8}) * di.cus;
+    // default: one workgroup per grid (the dispatcher balances the load) until
+    // there are several grids per resident workgroup; then each resident
+    // workgroup takes every nwg-th grid and prefetches the next one
+    t->persist = persist >= 0 ? persist : (ntasks > 4 * resident ? 1 : 0);
+    t->nwg = std::max(1, t->persist ? std::min(ntasks, resident) : ntasks);
 }
 
 }  // namespace
@@ -950,8 +956,8 @@ int autotune_group(sgh_plan *p, BatchGroup &bg) {
     }
     key << std::hex << h;
     std::vector<int> cached;
-    if (tune_get(key.str(), &cached) && cached.size() == 1) {
-        batch_default_tune(di, maxN, static_cast<int>(bg.grid_idx.size()), bg.dtype, &bg.tune, cached[0]);
+    if (tune_get(key.str(), &cached) && cached.size() == 2) {
+        batch_default_tune(di, maxN, static_cast<int>(bg.grid_idx.size()), bg.dtype, &bg.tune, cached[0], cached[1]);
         return SGH_OK;
     }
     const size_t es = esize_of(bg.dtype);
@@ -971,30 +977,33 @@ int autotune_group(sgh_plan *p, BatchGroup &bg) {
     if (e == hipSuccess) e = hipMemcpy(dtasks, tasks.data(), tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice);
     hipStream_t st = nullptr;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    int best_nt = 256;
+    int best_nt = 256, best_persist = 0;
     float best = 1e30f;
     if (e == hipSuccess) {
-        for (int nt : {128, 256, 512, 1024}) {
-            BatchTune t;
-            batch_default_tune(di, maxN, static_cast<int>(tasks.size()), bg.dtype, &t, nt);
-            if (t.nt != nt || (nt == 1024 && t.ept > 8)) continue;
-            const float ms = time_median(
-                [&](hipStream_t s) {
-                    return launch_batch(p->op, bg.dtype, dtasks, static_cast<int32_t>(tasks.size()), t, s);
-                },
-                st, 5);
-            if (ms < best) {
-                best = ms;
-                best_nt = nt;
+        for (int nt : {128, 256, 512, 1024})
+            for (int persist : {0, 1}) {
+                BatchTune t;
+                batch_default_tune(di, maxN, static_cast<int>(tasks.size()), bg.dtype, &t, nt, persist);
+                if (t.nt != nt || (nt == 1024 && t.ept > 8)) continue;
+                if (persist && t.nwg == static_cast<int>(tasks.size())) continue;  // same launch as persist = 0
+                const float ms = time_median(
+                    [&](hipStream_t s) {
+                        return launch_batch(p->op, bg.dtype, dtasks, static_cast<int32_t>(tasks.size()), t, s);
+                    },
+                    st, 5);
+                if (ms < best) {
+                    best = ms;
+                    best_nt = nt;
+                    best_persist = persist;
+                }
             }
-        }
     }
     if (st) (void)hipStreamDestroy(st);
     if (dtasks) (void)hipFree(dtasks);
     (void)hipFree(scratch);
     if (e != hipSuccess) return hip_fail(e, "autotune");
-    batch_default_tune(di, maxN, static_cast<int>(bg.grid_idx.size()), bg.dtype, &bg.tune, best_nt);
-    tune_put(key.str(), {best_nt});
+    batch_default_tune(di, maxN, static_cast<int>(bg.grid_idx.size()), bg.dtype, &bg.tune, best_nt, best_persist);
+    tune_put(key.str(), {best_nt, best_persist});
     return SGH_OK;
 }
 
@@ -1339,6 +1348,7 @@ int sgh_plan_describe(const sgh_plan *p, char *buf, int32_t len) {
         if (i) ss << ",";
         ss << "{\"dtype\":" << bg.dtype << ",\"tasks\":" << bg.grid_idx.size() << ",\"nt\":" << bg.tune.nt
            << ",\"ept\":" << bg.tune.ept << ",\"workgroups\":" << bg.tune.nwg << ",\"lds_bytes\":" << bg.tune.lds_bytes
+           << ",\"persistent\":" << bg.tune.persist
            << "}";
     }
     ss << "],\"large\":[";

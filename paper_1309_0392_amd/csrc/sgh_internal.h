@@ -133,8 +133,9 @@ struct PoleTune {
 struct BatchTune {
     int nt = 256;
     int ept = 8;
-    int nwg = 0;
+    int nwg = 0;        // one workgroup per grid, or the resident count (each then owns several grids)
     int lds_bytes = 0;
+    int persist = 0;    // 1: nwg = resident workgroups
 };
 
 // Launchers per element type and operation (return the first HIP error,
