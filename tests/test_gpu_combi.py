@@ -24,6 +24,7 @@ SETS = {
     "d2n5": lambda: W.combination_set(2, 5),
     "d3n6": lambda: W.combination_set(3, 6),
     "d4n10": lambda: W.combination_set(4, 10),
+    "d5n7": lambda: W.combination_set(5, 7),
     "single": lambda: ([(4, 3, 2)], [1.0]),
     "d1": lambda: ([(9,)], [1.0]),
     "aniso_random_coefs": lambda: ([(6, 2), (5, 3), (3, 4), (2, 6), (1, 8), (4, 4)],
