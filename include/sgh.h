@@ -102,8 +102,12 @@ int sgh_transform(int32_t op, const sgh_grid *grids, int32_t n, void *stream);
  * all of its launches into one HIP graph.  Grids that fit the on-chip tile
  * are transformed by one kernel launch with one workgroup per grid (largest
  * grids first), each grid loaded into LDS, transformed along all axes and
- * stored once; larger grids get their own launches, captured in the same graph.  This is the coarse "all combination grids in parallel"
- * level of the combination technique (Section 2).
+ * stored once.  Medium grids (too large for the tile, at most 2^18 points by
+ * default, at least 16 of them per dtype) go to a second launch with one
+ * workgroup per grid that takes the grid's axes in passes through its tile.
+ * The remaining grids get their own launches, captured in the same graph.
+ * This is the coarse "all combination grids in parallel" level of the
+ * combination technique (Section 2).
  *
  * flags: SGH_PLAN_GRAPH   capture into a hipGraph at creation when the plan
  *                          needs more than one launch (a single launch is
@@ -239,6 +243,13 @@ int sgh_set_split_spans(int32_t fine, int32_t coarse);
  * default (64 KiB boxes, 128-byte rows).  Applies to schedules and plans
  * built after the call; fusion level 0 forms no boxes. */
 int sgh_set_box_limits(int32_t max_bytes, int32_t min_row_bytes);
+
+/* Tuning knob for plans: grids larger than the on-chip tile with at most
+ * `max_points` points (0..2^24; 0 turns the medium launch off) go to the
+ * one-workgroup-per-grid medium launch when a plan holds at least `min_grids`
+ * (>= 1) of them of one dtype; otherwise each gets its own launches.  Defaults
+ * 2^18 and 16.  Applies to plans built after the call. */
+int sgh_set_medium_limits(int64_t max_points, int32_t min_grids);
 
 /* Schedule switch: level 1 (default) fuses the leading LDS-tile axes with one
  * strided axis walked in registers into a single launch (one HBM round trip

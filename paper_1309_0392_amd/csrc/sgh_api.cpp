@@ -807,7 +807,51 @@ struct PlanLarge {
     std::vector<Step> steps;
 };
 
+// Grids of a plan too large for one LDS tile but small enough that one
+// workgroup transforms each of them in passes through its tile (MedTask).
+struct MedGroup {
+    int dtype = SGH_F64;
+    std::vector<int> grid_idx;  // largest first
+    MedTask *dev_tasks = nullptr;
+};
+
 int batch_lds_limit(int dtype) { return dtype == SGH_F64 ? 8192 * 8 : 16384 * 4; }
+
+// A plan hands grids of at most g_medium_max points to the medium kernel when
+// it holds at least g_medium_min of them (of one element type); fewer go out
+// as per-grid launches, which then run at full-chip bandwidth each.
+int64_t g_medium_max = int64_t(1) << 18;
+int g_medium_min = 16;
+
+// Can one workgroup take grid g in passes through its tile?  Fills the task.
+bool medium_task(const Geom &g, MedTask *t) {
+    if (g.N > g_medium_max) return false;
+    const int64_t cap = tile_capacity(g.dtype);
+    int64_t Sm = 1;
+    const int m = tile_axes(g, &Sm);
+    if (m < 1 || m >= g.d) return false;
+    for (int k = m; k < g.d; ++k)
+        if (g.n[k] > cap) return false;
+    if (!t) return true;
+    *t = MedTask{};
+    t->data = g.data;
+    t->N = g.N;
+    t->d = g.d;
+    t->m = m;
+    t->chunk = static_cast<int32_t>((cap / Sm) * Sm);
+    t->tile = make_tile_geom(g, m);
+    for (int k = 0; k < g.d; ++k) {
+        t->L[k] = g.L[k];
+        t->n[k] = static_cast<int32_t>(g.n[k]);
+        t->st[k] = g.st[k];
+        if (k >= m) {
+            int W = 1;
+            while (2 * W * g.n[k] <= cap && W < g.st[k]) W *= 2;
+            t->W[k] = W;
+        }
+    }
+    return true;
+}
 
 void batch_default_tune(const DevInfo &di, int maxN, int ntasks, int dtype, BatchTune *t, int nt_pref = 0,
                         int persist = -1) {
@@ -853,6 +897,7 @@ struct sgh_plan {
     uint32_t flags = 0;
     std::vector<sgh_grid> grids;
     std::vector<sgh::BatchGroup> groups;
+    std::vector<sgh::MedGroup> medium;
     std::vector<sgh::PlanLarge> large;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -875,13 +920,27 @@ void fill_tasks(const sgh_plan &p, const BatchGroup &bg, std::vector<BatchTask> 
     }
 }
 
+void fill_med_tasks(const sgh_plan &p, const MedGroup &mg, std::vector<MedTask> *tasks) {
+    tasks->clear();
+    for (int gi : mg.grid_idx) {
+        MedTask t{};
+        (void)medium_task(make_geom(p.grids[gi]), &t);
+        tasks->push_back(t);
+    }
+}
+
+std::string op_prefix(int op) { return op == 0 ? "hier" : op == 1 ? "dehier" : "adjoint"; }
+
 hipError_t plan_launch_all(sgh_plan *p, hipStream_t st) {
     for (auto &bg : p->groups) {
-        TimerScope ts(std::string(p->op == 0 ? "hier" : p->op == 1 ? "dehier" : "adjoint") +
-                          (bg.dtype == SGH_F64 ? "_f64" : "_f32") + "_batch",
-                      st);
+        TimerScope ts(op_prefix(p->op) + (bg.dtype == SGH_F64 ? "_f64" : "_f32") + "_batch", st);
         hipError_t e =
             launch_batch(p->op, bg.dtype, bg.dev_tasks, static_cast<int32_t>(bg.grid_idx.size()), bg.tune, st);
+        if (e != hipSuccess) return e;
+    }
+    for (auto &mg : p->medium) {
+        TimerScope ts(op_prefix(p->op) + (mg.dtype == SGH_F64 ? "_f64" : "_f32") + "_medium", st);
+        hipError_t e = launch_medium(p->op, mg.dtype, mg.dev_tasks, static_cast<int32_t>(mg.grid_idx.size()), st);
         if (e != hipSuccess) return e;
     }
     for (auto &lg : p->large)
@@ -1155,6 +1214,9 @@ void plan_free(sgh_plan *p) {
     for (auto &bg : p->groups) {
         if (bg.dev_tasks) (void)hipFree(bg.dev_tasks);
     }
+    for (auto &mg : p->medium) {
+        if (mg.dev_tasks) (void)hipFree(mg.dev_tasks);
+    }
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
@@ -1166,6 +1228,12 @@ int plan_upload(sgh_plan *p) {
         std::vector<BatchTask> tasks;
         fill_tasks(*p, bg, &tasks);
         hipError_t e = hipMemcpy(bg.dev_tasks, tasks.data(), tasks.size() * sizeof(BatchTask), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "task upload");
+    }
+    for (auto &mg : p->medium) {
+        std::vector<MedTask> tasks;
+        fill_med_tasks(*p, mg, &tasks);
+        hipError_t e = hipMemcpy(mg.dev_tasks, tasks.data(), tasks.size() * sizeof(MedTask), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "task upload");
     }
     for (auto &lg : p->large) {
@@ -1255,20 +1323,40 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
     p->grids.assign(grids, grids + n);
     const DevInfo &di = dev_info();
     // split: grids that fit one workgroup's LDS go to the batch kernel
-    std::map<int, std::vector<std::pair<int64_t, int>>> small;
+    std::map<int, std::vector<std::pair<int64_t, int>>> small, medium;
+    std::vector<int> large;
     for (int i = 0; i < n; ++i) {
         Geom g = make_geom(grids[i]);
         p->points += g.N;
         if (g.d == 0) continue;  // all axes of level 1: identity
-        if (g.N * static_cast<int64_t>(esize_of(g.dtype)) <= batch_lds_limit(g.dtype)) {
+        if (g.N * static_cast<int64_t>(esize_of(g.dtype)) <= batch_lds_limit(g.dtype))
             small[g.dtype].push_back({g.N, i});
-        } else {
-            PlanLarge lg;
-            lg.grid = i;
-            lg.geom = g;
-            lg.steps = build_schedule(op, g);
-            p->large.push_back(lg);
+        else if (medium_task(g, nullptr))
+            medium[g.dtype].push_back({g.N, i});
+        else
+            large.push_back(i);
+    }
+    for (auto &kv : medium) {
+        auto v = kv.second;
+        if (static_cast<int>(v.size()) < g_medium_min) {
+            for (auto &x : v) large.push_back(x.second);
+            continue;
         }
+        std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+        MedGroup mg;
+        mg.dtype = kv.first;
+        for (auto &x : v) mg.grid_idx.push_back(x.second);
+        hipError_t e = hipMalloc(&mg.dev_tasks, v.size() * sizeof(MedTask));
+        if (e != hipSuccess) return hip_fail(e, "task list");
+        p->medium.push_back(mg);
+    }
+    std::sort(large.begin(), large.end());
+    for (int i : large) {
+        PlanLarge lg;
+        lg.grid = i;
+        lg.geom = make_geom(grids[i]);
+        lg.steps = build_schedule(op, lg.geom);
+        p->large.push_back(lg);
     }
     for (auto &kv : small) {
         BatchGroup bg;
@@ -1297,7 +1385,7 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
     if (rc) return rc;
     // a single launch goes out directly: replaying a one-node graph measured
     // slower than the launch it holds
-    size_t launches = p->groups.size();
+    size_t launches = p->groups.size() + p->medium.size();
     for (const auto &lg : p->large) launches += lg.steps.size();
     if ((flags & SGH_PLAN_GRAPH) && launches > 1) {
         rc = plan_capture(p.get());
@@ -1357,6 +1445,12 @@ int sgh_plan_describe(const sgh_plan *p, char *buf, int32_t len) {
            << ",\"ept\":" << bg.tune.ept << ",\"workgroups\":" << bg.tune.nwg << ",\"lds_bytes\":" << bg.tune.lds_bytes
            << ",\"persistent\":" << bg.tune.persist
            << "}";
+    }
+    ss << "],\"medium\":[";
+    for (size_t i = 0; i < p->medium.size(); ++i) {
+        const auto &mg = p->medium[i];
+        if (i) ss << ",";
+        ss << "{\"dtype\":" << mg.dtype << ",\"tasks\":" << mg.grid_idx.size() << "}";
     }
     ss << "],\"large\":[";
     for (size_t i = 0; i < p->large.size(); ++i) {
@@ -1422,6 +1516,17 @@ int sgh_set_box_limits(int32_t max_bytes, int32_t min_row_bytes) {
     std::lock_guard<std::mutex> lk(g_override_mu);
     g_box_bytes = max_bytes;
     g_box_row = min_row_bytes;
+    return SGH_OK;
+}
+
+int sgh_set_medium_limits(int64_t max_points, int32_t min_grids) {
+    using namespace sgh;
+    if (max_points < 0 || max_points > (int64_t(1) << 24) || min_grids < 1)
+        return fail(SGH_ERR_ARG, "medium limits %lld, %d outside 0..2^24, >= 1", static_cast<long long>(max_points),
+                    min_grids);
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    g_medium_max = max_points;
+    g_medium_min = min_grids;
     return SGH_OK;
 }
 

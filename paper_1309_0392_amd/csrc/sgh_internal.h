@@ -45,6 +45,24 @@ struct BatchTask {
     TileGeom g;
 };
 
+// A grid of a batched plan too large for one LDS tile, transformed by one
+// workgroup in passes through its tile: the leading tile axes in chunks of
+// whole tiles, then every further axis in boxes of W adjacent columns times
+// the whole pole (inverse and transpose: the passes in reverse).
+struct MedTask {
+    void *data;
+    int64_t N;
+    int32_t d;      // axes (level-1 axes dropped)
+    int32_t m;      // leading axes of the tile pass
+    int32_t chunk;  // elements per tile chunk (whole tiles)
+    int32_t pad;
+    TileGeom tile;  // the tile pass's axes
+    int32_t L[kMaxDim];
+    int32_t n[kMaxDim];
+    int64_t st[kMaxDim];
+    int32_t W[kMaxDim];  // columns per box of axis k >= m, a power of two
+};
+
 // Strided axis: npoles = outer * S poles of n = 2^L - 1 points at stride S.
 // split 2: blocks of span 2^B between coarse points (2^(L-B) blocks);
 // split 3: 2^TB super-blocks of 2^B blocks of span 2^B (L = TB + 2B), with the
@@ -146,6 +164,7 @@ struct BatchTune {
     hipError_t launch_tw_##SUF(const TWLaunch &p, hipStream_t s);                                     \
     hipError_t launch_split_##SUF(const SplitLaunch &p, hipStream_t s);                               \
     hipError_t launch_box_##SUF(const BoxLaunch &p, const TileTune &t, hipStream_t s);                \
+    hipError_t launch_medium_##SUF(const MedTask *dev_tasks, int32_t ntasks, hipStream_t s);          \
     hipError_t launch_batch_##SUF(const BatchTask *dev_tasks, int32_t ntasks, const BatchTune &t,    \
                                   hipStream_t s);
 SGH_DECLARE_LAUNCHERS(f64_h)
@@ -182,6 +201,9 @@ inline hipError_t launch_split(int op, int dtype, const SplitLaunch &p, hipStrea
 }
 inline hipError_t launch_box(int op, int dtype, const BoxLaunch &p, const TileTune &t, hipStream_t s) {
     SGH_ROUTE(launch_box, p, t, s);
+}
+inline hipError_t launch_medium(int op, int dtype, const MedTask *dev_tasks, int32_t ntasks, hipStream_t s) {
+    SGH_ROUTE(launch_medium, dev_tasks, ntasks, s);
 }
 inline hipError_t launch_batch(int op, int dtype, const BatchTask *dev_tasks, int32_t ntasks, const BatchTune &t,
                                hipStream_t s) {

@@ -82,6 +82,7 @@ def lib():
             "sgh_set_walk_preference": ([i32], ctypes.c_int),
             "sgh_set_split_spans": ([i32, i32], ctypes.c_int),
             "sgh_set_box_limits": ([i32, i32], ctypes.c_int),
+            "sgh_set_medium_limits": ([i64, i32], ctypes.c_int),
             "sgh_timing_reset": ([], ctypes.c_int),
             "sgh_timing_report": ([ctypes.c_char_p, i32], ctypes.c_int),
             "sgh_combi_create": ([ctypes.POINTER(vp), G, i32, ctypes.POINTER(ctypes.c_double), u32],
@@ -382,6 +383,12 @@ def set_split_spans(fine: int = 0, coarse: int = 0):
 def set_box_limits(max_bytes: int = 0, min_row_bytes: int = 0):
     """Size limits of the launches that transform runs of small strided axes together (0 = default)."""
     _check(lib().sgh_set_box_limits(int(max_bytes), int(min_row_bytes)), "sgh_set_box_limits")
+
+
+def set_medium_limits(max_points: int = 1 << 18, min_grids: int = 16):
+    """Plans: grids above the tile with at most max_points points go to the one-workgroup-per-grid
+    launch when there are at least min_grids of them (max_points 0 turns it off)."""
+    _check(lib().sgh_set_medium_limits(int(max_points), int(min_grids)), "sgh_set_medium_limits")
 
 
 def set_walk_preference(pref: int):

@@ -208,3 +208,12 @@ def test_fusion_switch():
     finally:
         sgh.set_fusion(1)
         sgh.set_pole_split(9, 0, 0, 0)
+
+
+def test_medium_limits_knob():
+    sgh.set_medium_limits(0, 1)  # 0 turns the medium launch off
+    sgh.set_medium_limits(1 << 24, 100)
+    sgh.set_medium_limits()
+    for bad in ((-1, 16), ((1 << 24) + 1, 16), (1 << 18, 0)):
+        with pytest.raises(sgh.SghError):
+            sgh.set_medium_limits(*bad)
