@@ -200,7 +200,11 @@ def secondary_combination(args, torch, np, sgh, W, name):
 
 def secondary_batch(args, torch, np, sgh, W, name):
     """The d=4, n=10 combination set as one batched plan; `batch128` holds 128 copies
-    of the set (75,392 grids, 1.0 GB FP64) so that HBM, not latency, bounds it."""
+    of the set (75,392 grids, 1.0 GB FP64) so that HBM, not latency, bounds it;
+    `batch_d4n13` is the d=4, n=13 set (1,325 grids, 165 MB FP64), whose grids above
+    the LDS tile go to the medium launch."""
+    if name == "batch_d4n13":
+        return secondary_medium(args, torch, np, sgh, W, name)
     lv, co = W.combination_set()
     R = 128 if name == "batch128" else 1
     xs = [torch.from_numpy(a).cuda() for _ in range(R) for a in W.combination_values(lv, seed=3)]
@@ -221,8 +225,32 @@ def secondary_batch(args, torch, np, sgh, W, name):
     return out
 
 
+def secondary_medium(args, torch, np, sgh, W, name):
+    """The d=4, n=13 combination set as one plan: a batch launch for the grids that fit
+    the LDS tile and a medium launch (one workgroup per grid, passes through its tile)."""
+    lv, _ = W.combination_set(4, 13)
+    xs = [torch.from_numpy(a).cuda() for a in W.combination_values(lv, seed=3)]
+    npts = sum(t.numel() for t in xs)
+    plan = sgh.Plan(sgh.OP_HIERARCHIZE, xs, lv, graph=False)  # two launches, timed one by one
+    desc = plan.describe()
+    pts = {"hier_f64_batch": sum(b["points"] for b in desc["batches"]),
+           "hier_f64_medium": sum(m["points"] for m in desc["medium"])}
+    for _ in range(args.warmup):
+        plan.execute()
+    ms, rep = timed_kernels(torch, sgh, plan.execute, args.steps)
+    out = {"metric": "grid points hierarchized/s (batched combination set)", "unit": "points/s",
+           "value": npts / (ms * 1e-3), "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "the d=4, n=13 combination set: %d grids, %d points (%d in medium grids), FP64"
+                                  % (len(lv), npts, pts["hier_f64_medium"])},
+           "kernels": kernel_table(rep), "plan": {"batches": desc["batches"], "medium": desc["medium"]},
+           "roofline": roofline_of(rep, lambda k: 2.0 * pts.get(k, npts) * 8, name, dominant="hier_f64_medium")}
+    plan.close()
+    return out
+
+
 SECONDARY = {"pole27": secondary_grid, "tend12": secondary_grid, "combi_d4n15": secondary_combination,
-             "batch": secondary_batch, "batch128": secondary_batch}
+             "batch": secondary_batch, "batch128": secondary_batch, "batch_d4n13": secondary_batch}
 
 
 def main():

@@ -823,12 +823,18 @@ int batch_lds_limit(int dtype) { return dtype == SGH_F64 ? 8192 * 8 : 16384 * 4;
 int64_t g_medium_max = int64_t(1) << 18;
 int g_medium_min = 16;
 
-// Can one workgroup take grid g in passes through its tile?  Fills the task.
+// Can one workgroup take grid g in passes through its tile?  Fills the task:
+// after the tile pass, runs of consecutive axes share one box pass while the
+// box keeps rows of at least 128 bytes (or every column of the run's stride).
 bool medium_task(const Geom &g, MedTask *t) {
     if (g.N > g_medium_max) return false;
-    const int64_t cap = tile_capacity(g.dtype);
+    const int64_t cap = kMedTileBytes / static_cast<int64_t>(esize_of(g.dtype));
+    int m = 0;
     int64_t Sm = 1;
-    const int m = tile_axes(g, &Sm);
+    while (m < g.d && Sm * g.n[m] <= cap) {
+        Sm *= g.n[m];
+        ++m;
+    }
     if (m < 1 || m >= g.d) return false;
     for (int k = m; k < g.d; ++k)
         if (g.n[k] > cap) return false;
@@ -836,7 +842,6 @@ bool medium_task(const Geom &g, MedTask *t) {
     *t = MedTask{};
     t->data = g.data;
     t->N = g.N;
-    t->d = g.d;
     t->m = m;
     t->chunk = static_cast<int32_t>((cap / Sm) * Sm);
     t->tile = make_tile_geom(g, m);
@@ -844,11 +849,30 @@ bool medium_task(const Geom &g, MedTask *t) {
         t->L[k] = g.L[k];
         t->n[k] = static_cast<int32_t>(g.n[k]);
         t->st[k] = g.st[k];
-        if (k >= m) {
-            int W = 1;
-            while (2 * W * g.n[k] <= cap && W < g.st[k]) W *= 2;
-            t->W[k] = W;
+    }
+    // widest power-of-two column count for R rows at stride S
+    auto width = [&](int64_t R, int64_t S) {
+        int64_t W = 1;
+        while (2 * W * R <= cap && W < S) W *= 2;
+        return W;
+    };
+    const int64_t min_w = 128 / static_cast<int64_t>(esize_of(g.dtype));
+    int k = m;
+    while (k < g.d) {
+        const int64_t S = g.st[k];
+        int64_t R = g.n[k];
+        int k1 = k + 1;
+        while (k1 < g.d && R * g.n[k1] <= cap) {
+            const int64_t W = width(R * g.n[k1], S);
+            if (W < min_w && W < S) break;
+            R *= g.n[k1];
+            ++k1;
         }
+        const int p = t->npass++;
+        t->k0[p] = k;
+        t->k1[p] = k1;
+        t->W[p] = static_cast<int32_t>(width(R, S));
+        k = k1;
     }
     return true;
 }
@@ -1441,7 +1465,10 @@ int sgh_plan_describe(const sgh_plan *p, char *buf, int32_t len) {
     for (size_t i = 0; i < p->groups.size(); ++i) {
         const auto &bg = p->groups[i];
         if (i) ss << ",";
-        ss << "{\"dtype\":" << bg.dtype << ",\"tasks\":" << bg.grid_idx.size() << ",\"nt\":" << bg.tune.nt
+        int64_t pts = 0;
+        for (int gi : bg.grid_idx) pts += make_geom(p->grids[gi]).N;
+        ss << "{\"dtype\":" << bg.dtype << ",\"tasks\":" << bg.grid_idx.size() << ",\"points\":" << pts
+           << ",\"nt\":" << bg.tune.nt
            << ",\"ept\":" << bg.tune.ept << ",\"workgroups\":" << bg.tune.nwg << ",\"lds_bytes\":" << bg.tune.lds_bytes
            << ",\"persistent\":" << bg.tune.persist
            << "}";
@@ -1450,7 +1477,10 @@ int sgh_plan_describe(const sgh_plan *p, char *buf, int32_t len) {
     for (size_t i = 0; i < p->medium.size(); ++i) {
         const auto &mg = p->medium[i];
         if (i) ss << ",";
-        ss << "{\"dtype\":" << mg.dtype << ",\"tasks\":" << mg.grid_idx.size() << "}";
+        int64_t pts = 0;
+        for (int gi : mg.grid_idx) pts += make_geom(p->grids[gi]).N;
+        ss << "{\"dtype\":" << mg.dtype << ",\"tasks\":" << mg.grid_idx.size() << ",\"points\":" << pts
+           << ",\"tile_bytes\":" << kMedTileBytes << "}";
     }
     ss << "],\"large\":[";
     for (size_t i = 0; i < p->large.size(); ++i) {

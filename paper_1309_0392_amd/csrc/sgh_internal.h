@@ -45,22 +45,50 @@ struct BatchTask {
     TileGeom g;
 };
 
+// The medium launch's tile (bytes of LDS per workgroup), elements per thread
+// (FP64, FP32; the workgroup size follows), and whether the next step's
+// values are loaded while the current step is transformed.
+#ifndef SGH_MEDIUM_TILE_BYTES
+#define SGH_MEDIUM_TILE_BYTES 65536
+#endif
+#ifndef SGH_MEDIUM_EPT64
+#define SGH_MEDIUM_EPT64 16
+#endif
+#ifndef SGH_MEDIUM_EPT32
+#define SGH_MEDIUM_EPT32 16
+#endif
+#ifndef SGH_MEDIUM_PREFETCH
+#define SGH_MEDIUM_PREFETCH 1
+#endif
+// Minimum waves per SIMD the medium kernel is compiled for (0: the compiler's choice).
+#ifndef SGH_MEDIUM_WAVES
+#define SGH_MEDIUM_WAVES 0
+#endif
+constexpr int kMedTileBytes = SGH_MEDIUM_TILE_BYTES;
+constexpr int kMedEpt64 = SGH_MEDIUM_EPT64;
+constexpr int kMedEpt32 = SGH_MEDIUM_EPT32;
+constexpr bool kMedPrefetch = SGH_MEDIUM_PREFETCH != 0;
+
 // A grid of a batched plan too large for one LDS tile, transformed by one
 // workgroup in passes through its tile: the leading tile axes in chunks of
-// whole tiles, then every further axis in boxes of W adjacent columns times
-// the whole pole (inverse and transpose: the passes in reverse).
+// whole tiles, then runs of consecutive further axes k0..k1-1, each run in
+// boxes of W adjacent columns times the run's whole extent (consecutive axes
+// have strides S, S*n_k0, ..., so the box is W columns by n_k0*...*n_(k1-1)
+// rows at stride S).  Inverse and transpose take the passes in reverse.
 struct MedTask {
     void *data;
     int64_t N;
-    int32_t d;      // axes (level-1 axes dropped)
     int32_t m;      // leading axes of the tile pass
     int32_t chunk;  // elements per tile chunk (whole tiles)
+    int32_t npass;  // box passes after the tile pass
     int32_t pad;
     TileGeom tile;  // the tile pass's axes
     int32_t L[kMaxDim];
     int32_t n[kMaxDim];
     int64_t st[kMaxDim];
-    int32_t W[kMaxDim];  // columns per box of axis k >= m, a power of two
+    int32_t k0[kMaxDim];  // box pass p takes axes k0[p] .. k1[p]-1
+    int32_t k1[kMaxDim];
+    int32_t W[kMaxDim];   // columns per box of pass p, a power of two
 };
 
 // Strided axis: npoles = outer * S poles of n = 2^L - 1 points at stride S.
