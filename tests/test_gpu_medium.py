@@ -80,10 +80,12 @@ def test_d3n13_set_f32(op):
 
 # Shapes at the kernel's limits: an axis of 8191 points after a 3-point tile
 # (one column per box), a full tile row followed by a short axis with ragged
-# boxes, level-1 axes in between, five axes, FP32 rows of 16383 points.
+# boxes, level-1 axes in between and two box passes, five axes, FP32 rows of
+# 16383 points, two and three trailing axes sharing one box pass.
 EDGE = [((2, 13), np.float64), ((13, 2), np.float64), ((3, 1, 11, 1, 2), np.float64),
         ((4, 3, 3, 3, 3), np.float64), ((12, 3), np.float64), ((14, 2), np.float32),
-        ((2, 14), np.float32), ((5, 5, 5), np.float32), ((1, 9, 6), np.float64)]
+        ((2, 14), np.float32), ((5, 5, 5), np.float32), ((1, 9, 6), np.float64),
+        ((6, 6, 2, 2), np.float64), ((7, 2, 2, 2, 2, 2, 2), np.float32), ((9, 3, 2, 2, 2), np.float64)]
 
 
 @pytest.mark.parametrize("op", list(ORACLE), ids=lambda o: OP_NAME[o])
