@@ -466,9 +466,12 @@ BoxLimits box_limits() {
     return b;
 }
 
+// Largest box the box kernel is built for: 512 threads of at most 32 elements.
+constexpr int64_t kBoxMaxElems = 512 * 32;
+
 int box_width(int64_t P, int esize, const BoxLimits &lim) {
     for (int W : {64, 32, 16})
-        if (P * W * esize <= lim.bytes && W * esize >= lim.row) return W;
+        if (P * W * esize <= lim.bytes && P * W <= kBoxMaxElems && W * esize >= lim.row) return W;
     return 0;
 }
 
@@ -721,8 +724,33 @@ std::string step_timer_name(int op, int dtype, const Step &s) {
     return ss.str();
 }
 
+// Launch preconditions of one step (a kernel instantiation exists for it),
+// checked for every step of a grid before the first of them is launched, so
+// that a grid is never left partly transformed.
+bool step_launchable(const Step &s) {
+    switch (s.kind) {
+        case Step::TILE:
+            return tile_ept_supported(s.ttune.ept) && (s.ttune.nt == 128 || s.ttune.nt == 256 || s.ttune.nt == 512) &&
+                   static_cast<int64_t>(s.ttune.nt) * s.ttune.ept >= s.tile.chunk;
+        case Step::BOX:
+            return (s.ttune.ept == 4 || s.ttune.ept == 8 || s.ttune.ept == 16 || s.ttune.ept == 32) &&
+                   (s.ttune.nt == 256 || s.ttune.nt == 512) &&
+                   static_cast<int64_t>(s.box.P) * s.box.W <= static_cast<int64_t>(s.ttune.nt) * s.ttune.ept;
+        case Step::POLE:
+            return s.pole.split == 3 ? pole3_supported(s.pole.L, s.pole.TB, s.pole.B) && s.ptune.nt == 256
+                                     : pole_supported(s.pole.L, s.pole.B);
+        case Step::TW:
+            return s.tw.split == 3 ? s.tw.ept == 1 && tw3_supported(s.tw.L, s.tw.TB, s.tw.B)
+                                   : tw_supported(s.tw.L, s.tw.B, s.tw.ept);
+        case Step::SPLIT:
+            return s.split.W >= 1 && s.split.W <= 64 && s.split.Bs >= 1 && s.split.Bs <= s.split.L - s.split.E;
+        default:
+            return false;
+    }
+}
+
 hipError_t run_step(int op, int dtype, const Step &s, hipStream_t st) {
-    if (s.kind == Step::TILE && static_cast<int64_t>(s.ttune.nt) * s.ttune.ept < s.tile.chunk) return hipErrorInvalidValue;
+    if (!step_launchable(s)) return hipErrorInvalidValue;
     TimerScope ts(step_timer_name(op, dtype, s), st);
     switch (s.kind) {
         case Step::TILE: return launch_tile(op, dtype, s.tile, s.ttune, st);
@@ -781,11 +809,18 @@ int transform(int op, const sgh_grid *grids, int32_t n, void *stream) {
     int rc = validate_all(grids, n);
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<std::vector<Step>> all(static_cast<size_t>(n));
     for (int i = 0; i < n; ++i) {
-        Geom g = make_geom(grids[i]);
-        auto steps = build_schedule(op, g);
-        for (auto &s : steps) {
-            hipError_t e = run_step(op, g.dtype, s, st);
+        all[static_cast<size_t>(i)] = build_schedule(op, make_geom(grids[i]));
+        for (auto &s : all[static_cast<size_t>(i)])
+            if (!step_launchable(s))
+                return fail(SGH_ERR_UNSUPPORTED, "grid %d: no %s kernel for this shape under the current tuning knobs", i,
+                            step_name(s));
+    }
+    for (int i = 0; i < n; ++i) {
+        const int dtype = grids[i].dtype;
+        for (auto &s : all[static_cast<size_t>(i)]) {
+            hipError_t e = run_step(op, dtype, s, st);
             if (e != hipSuccess) return hip_fail(e, "kernel launch");
         }
     }
@@ -1405,6 +1440,11 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
             if (rc) return rc;
         }
     }
+    for (const auto &lg : p->large)
+        for (const auto &s : lg.steps)
+            if (!step_launchable(s))
+                return fail(SGH_ERR_UNSUPPORTED, "grid %d: no %s kernel for this shape under the current tuning knobs",
+                            lg.grid, step_name(s));
     rc = plan_upload(p.get());
     if (rc) return rc;
     // a single launch goes out directly: replaying a one-node graph measured

@@ -181,6 +181,26 @@ def test_box_schedules():
         sgh.set_box_limits(-1, 0)
 
 
+def test_box_limits_whole_range_launchable():
+    # every box the knob's accepted range can form has a kernel instantiation:
+    # 256 or 512 threads of 4..32 elements covering the box
+    shapes = [(13, 3, 3, 3, 3), (12,) + (2,) * 9, (4, 5, 5, 5), (2,) * 12, (6, 6, 5, 5, 5), (3, 2, 4, 3, 2, 5)]
+    try:
+        for max_bytes in list(range(0, 160 * 1024 + 1, 4096)) + [160 * 1024]:
+            for row in (0, 16, 64, 128, 512):
+                sgh.set_box_limits(max_bytes, row)
+                for lv in shapes:
+                    for dt in (sgh.F32, sgh.F64):
+                        for op in (sgh.OP_HIERARCHIZE, sgh.OP_ADJOINT):
+                            for l in sgh.schedule(op, lv, dt)["launches"]:
+                                if l["kind"] != "box":
+                                    continue
+                                assert l["nt"] in (256, 512) and l["ept"] in (4, 8, 16, 32), (max_bytes, row, lv, l)
+                                assert l["box"] <= l["nt"] * l["ept"], (max_bytes, row, lv, l)
+    finally:
+        sgh.set_box_limits(0, 0)
+
+
 def test_fusion_switch():
     try:
         sgh.set_fusion(0)
