@@ -102,9 +102,13 @@ int sgh_transform(int32_t op, const sgh_grid *grids, int32_t n, void *stream);
  * all of its launches into one HIP graph.  Grids that fit the on-chip tile
  * are transformed by one kernel launch with one workgroup per grid (largest
  * grids first), each grid loaded into LDS, transformed along all axes and
- * stored once.  Medium grids (too large for the tile, at most 2^18 points by
- * default, at least 16 of them per dtype) go to a second launch with one
- * workgroup per grid that takes the grid's axes in passes through its tile.
+ * stored once.  A set of many such grids (4096 or more of one dtype by
+ * default, see sgh_set_batch_classes) is split into size classes by bytes
+ * (up to 8, 16, 32 and 64 KiB), one launch each, so that each launch's
+ * workgroups and LDS tiles fit its grids.  Medium grids (too large for the
+ * tile, at most 2^18 points by default, at least 16 of them per dtype) go to
+ * a second launch with one workgroup per grid that takes the grid's axes in
+ * passes through its tile.
  * The remaining grids get their own launches, captured in the same graph.
  * This is the coarse "all combination grids in parallel" level of the
  * combination technique (Section 2).
@@ -115,15 +119,32 @@ int sgh_transform(int32_t op, const sgh_grid *grids, int32_t n, void *stream);
  *        SGH_PLAN_AUTOTUNE time candidate tile configurations on scratch
  *                          buffers at creation and keep the fastest (results
  *                          are cached per device, op, dtype and level set).
+ *        SGH_PLAN_RELATIVE the descriptors' data fields are byte offsets
+ *                          (0 allowed, aligned to the element size) into one
+ *                          buffer that is named at each execution
+ *                          (sgh_plan_execute_at); such a plan never captures
+ *                          a graph.  For callers that keep a whole set in one
+ *                          allocation whose address changes between calls
+ *                          (autograd buffers), without re-uploading the task
+ *                          list or synchronizing.
  * The plan does not own the grid buffers; they must outlive every execute.
  */
 #define SGH_PLAN_GRAPH 1u
 #define SGH_PLAN_AUTOTUNE 2u
+#define SGH_PLAN_RELATIVE 4u
 
 typedef struct sgh_plan sgh_plan;
 
 int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t n, uint32_t flags);
+/* Executes a plan on `stream` (NULL = default stream).  SGH_ERR_ARG for a
+ * relative plan. */
 int sgh_plan_execute(sgh_plan *plan, void *stream);
+/* Executes a relative plan (SGH_PLAN_RELATIVE) on the grids at base + offset:
+ * base is a device pointer aligned to every grid's element size; the buffer
+ * must hold every grid of the plan.  Allocates nothing; the same launches as
+ * sgh_plan_execute.  SGH_ERR_ARG for a plan created without the flag or a
+ * null base, SGH_ERR_ALIGN for a misaligned base. */
+int sgh_plan_execute_at(sgh_plan *plan, void *base, void *stream);
 /* Repoint the plan to new buffers of identical shapes and dtypes (same n,
  * same order).  Synchronizes the device first (an execute in flight may still
  * read the old task list), then rewrites the device task list; the graph is
@@ -250,6 +271,13 @@ int sgh_set_box_limits(int32_t max_bytes, int32_t min_row_bytes);
  * (>= 1) of them of one dtype; otherwise each gets its own launches.  Defaults
  * 2^18 and 16.  Applies to plans built after the call. */
 int sgh_set_medium_limits(int64_t max_points, int32_t min_grids);
+
+/* Tuning knob for plans: the small grids of one dtype are split into size
+ * classes (one batch launch per class of up to 8, 16, 32, 64 KiB per grid)
+ * when there are at least `min_grids` of them (0: never split); a class of
+ * fewer than `min_per_class` (>= 1) grids joins the next larger class.
+ * Defaults 4096 and 1024.  Applies to plans built after the call. */
+int sgh_set_batch_classes(int32_t min_grids, int32_t min_per_class);
 
 /* Schedule switch: level 1 (default) fuses the leading LDS-tile axes with one
  * strided axis walked in registers into a single launch (one HBM round trip

@@ -31,48 +31,73 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# the same source built with OpenMP: the pole loops shared over the host's
+# cores (used only to time the oracle on all cores; same arithmetic per pole)
+_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 _lib = None
+_lib_omp = None
+
+
+def _compile(out: str, extra) -> None:
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared"] + list(extra) + ["-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, out)
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c with gcc (-O2, no fast-math) into liboracle.so."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB_PATH)
+    """Compile oracle.c with gcc (-O2, no fast-math) into liboracle.so, and the
+    OpenMP build liboracle_omp.so."""
+    for path, extra in ((_LIB_PATH, []), (_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            _compile(path, extra)
     return _LIB_PATH
 
 
-def _load():
-    global _lib
+def _bind(lib):
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lp = ctypes.POINTER(ctypes.c_int64)
+    for name in ("oracle_hierarchize", "oracle_dehierarchize", "oracle_hierarchize_adjoint"):
+        f = getattr(lib, name)
+        f.argtypes = [dp, ctypes.c_int, ip]
+        f.restype = ctypes.c_int
+    for name in ("oracle_hierarchize_axis", "oracle_dehierarchize_axis",
+                 "oracle_hierarchize_adjoint_axis"):
+        f = getattr(lib, name)
+        f.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int]
+        f.restype = ctypes.c_int
+    for name in ("oracle_hierarchize_point", "oracle_dehierarchize_point",
+                 "oracle_hierarchize_adjoint_point"):
+        f = getattr(lib, name)
+        f.argtypes = [dp, ctypes.c_int, ip, lp]
+        f.restype = ctypes.c_double
+    for name in ("oracle_flops_eq1", "oracle_mults_reduced"):
+        f = getattr(lib, name)
+        f.argtypes = [ctypes.c_int, ip]
+        f.restype = ctypes.c_double
+    lib.oracle_num_points.argtypes = [ctypes.c_int, ip]
+    lib.oracle_num_points.restype = ctypes.c_int64
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
+    return lib
+
+
+def _load(threads: bool = False):
+    global _lib, _lib_omp
+    if threads:
+        if _lib_omp is None:
+            build()
+            _lib_omp = _bind(ctypes.CDLL(_OMP_PATH))
+        return _lib_omp
     if _lib is None:
         build()
-        lib = ctypes.CDLL(_LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        ip = ctypes.POINTER(ctypes.c_int)
-        lp = ctypes.POINTER(ctypes.c_int64)
-        for name in ("oracle_hierarchize", "oracle_dehierarchize", "oracle_hierarchize_adjoint"):
-            f = getattr(lib, name)
-            f.argtypes = [dp, ctypes.c_int, ip]
-            f.restype = ctypes.c_int
-        for name in ("oracle_hierarchize_axis", "oracle_dehierarchize_axis",
-                     "oracle_hierarchize_adjoint_axis"):
-            f = getattr(lib, name)
-            f.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int]
-            f.restype = ctypes.c_int
-        for name in ("oracle_hierarchize_point", "oracle_dehierarchize_point",
-                     "oracle_hierarchize_adjoint_point"):
-            f = getattr(lib, name)
-            f.argtypes = [dp, ctypes.c_int, ip, lp]
-            f.restype = ctypes.c_double
-        for name in ("oracle_flops_eq1", "oracle_mults_reduced"):
-            f = getattr(lib, name)
-            f.argtypes = [ctypes.c_int, ip]
-            f.restype = ctypes.c_double
-        lib.oracle_num_points.argtypes = [ctypes.c_int, ip]
-        lib.oracle_num_points.restype = ctypes.c_int64
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(_LIB_PATH))
     return _lib
+
+
+def num_threads(threads: bool = False) -> int:
+    """Threads the pole loops use (1 for the plain build)."""
+    return int(_load(threads).oracle_threads())
 
 
 def shape_of(levels) -> tuple:
@@ -92,8 +117,8 @@ def _check(x: np.ndarray, levels):
         raise ValueError("shape %s does not match levels %s" % (x.shape, tuple(levels)))
 
 
-def _run(name, x, levels, *extra):
-    lib = _load()
+def _run(name, x, levels, *extra, threads: bool = False):
+    lib = _load(threads)
     y = np.array(x, dtype=np.float64, order="C", copy=True)
     _check(y, levels)
     lv, d = _levels_arg(levels)
@@ -103,17 +128,36 @@ def _run(name, x, levels, *extra):
     return y
 
 
-def hierarchize(x, levels) -> np.ndarray:
-    """Algorithm 1 on a copy of x (float64)."""
-    return _run("oracle_hierarchize", x, levels)
+def hierarchize(x, levels, threads: bool = False) -> np.ndarray:
+    """Algorithm 1 on a copy of x (float64); threads=True runs the poles of
+    each direction on all cores (OpenMP build)."""
+    return _run("oracle_hierarchize", x, levels, threads=threads)
 
 
-def dehierarchize(x, levels) -> np.ndarray:
-    return _run("oracle_dehierarchize", x, levels)
+def dehierarchize(x, levels, threads: bool = False) -> np.ndarray:
+    return _run("oracle_dehierarchize", x, levels, threads=threads)
 
 
-def hierarchize_adjoint(x, levels) -> np.ndarray:
-    return _run("oracle_hierarchize_adjoint", x, levels)
+def hierarchize_adjoint(x, levels, threads: bool = False) -> np.ndarray:
+    return _run("oracle_hierarchize_adjoint", x, levels, threads=threads)
+
+
+def hierarchize_inplace(x: np.ndarray, levels, threads: bool = False) -> np.ndarray:
+    """Algorithm 1 applied to x itself (C-contiguous float64), for timing the
+    oracle without the copy the other entry points make."""
+    _check(x, levels)
+    lv, d = _levels_arg(levels)
+    if _load(threads).oracle_hierarchize(x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), d, lv) != 0:
+        raise ValueError("oracle_hierarchize rejected levels %s" % (tuple(levels),))
+    return x
+
+
+def hierarchize_adjoint_inplace(x: np.ndarray, levels, threads: bool = False) -> np.ndarray:
+    _check(x, levels)
+    lv, d = _levels_arg(levels)
+    if _load(threads).oracle_hierarchize_adjoint(x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), d, lv) != 0:
+        raise ValueError("oracle_hierarchize_adjoint rejected levels %s" % (tuple(levels),))
+    return x
 
 
 def hierarchize_axis(x, levels, axis: int) -> np.ndarray:

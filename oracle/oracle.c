@@ -41,6 +41,9 @@
  */
 #include <stdint.h>
 #include <stddef.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORACLE_MAX_DIM 16
 
@@ -137,9 +140,23 @@ static void for_all_poles(double *x, int d, const int *level, int k, pole_fn fn)
     const int64_t st = axis_stride(d, level, k);
     const int64_t total = oracle_num_points(d, level);
     const int64_t outer = total / (n * st);
+    /* The poles are disjoint, so they may run on several threads: built with
+     * OpenMP (the multi-core timing build) they are shared out statically;
+     * the arithmetic of each pole is the same either way. */
+#pragma omp parallel for collapse(2) schedule(static)
     for (int64_t o = 0; o < outer; ++o)
         for (int64_t s = 0; s < st; ++s)
             fn(x + o * n * st + s, st, L);
+}
+
+/* Threads the pole loops use: 1, or OpenMP's count in the multi-core build. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 static int check_args(const double *x, int d, const int *level)

@@ -3,6 +3,7 @@
 
     y = hierarchize(u, levels)                 # one grid
     ys = hierarchize_batch(us, levels_list)    # a combination-grid set, one plan
+    y = hierarchize_flat(u, levels_list)       # a set stored back to back in one tensor
 
 Both are out of place (the input is cloned, then transformed in place on the
 GPU).  The backward of y = H u is  grad_u = H^T grad_y,  computed by the
@@ -76,3 +77,42 @@ class HierarchizeBatch(torch.autograd.Function):
 def hierarchize_batch(us: Sequence[torch.Tensor], levels_list) -> List[torch.Tensor]:
     levels = tuple(tuple(int(l) for l in lv) for lv in levels_list)
     return list(HierarchizeBatch.apply(levels, *us))
+
+
+_FLAT: Dict[tuple, "sgh.FlatPlan"] = {}
+
+
+def flat_plan(op: int, levels: Tuple[Tuple[int, ...], ...], dtype: torch.dtype, device: torch.device) -> "sgh.FlatPlan":
+    """The cached relative plan of a set stored back to back (one per op, level list, dtype, device)."""
+    key = (op, levels, dtype, device.index)
+    plan = _FLAT.get(key)
+    if plan is None:
+        with torch.cuda.device(device):
+            plan = sgh.FlatPlan(op, levels, sgh.F64 if dtype == torch.float64 else sgh.F32)
+        _FLAT[key] = plan
+    return plan
+
+
+class HierarchizeFlat(torch.autograd.Function):
+    """A combination set held back to back in one flat tensor (grid i at
+    FlatPlan.starts[i]): forward hierarchizes a copy, backward applies the
+    adjoint kernels to a copy of the incoming gradient, each as the launches of
+    one relative plan (no task-list upload, no synchronization)."""
+
+    @staticmethod
+    def forward(ctx, u: torch.Tensor, levels: Tuple[Tuple[int, ...], ...]):
+        ctx.levels = levels
+        y = u.detach().contiguous().clone()
+        flat_plan(sgh.OP_HIERARCHIZE, levels, y.dtype, y.device).execute(y)
+        return y
+
+    @staticmethod
+    def backward(ctx, grad_y: torch.Tensor):
+        g = grad_y.detach().contiguous().clone()
+        flat_plan(sgh.OP_ADJOINT, ctx.levels, g.dtype, g.device).execute(g)
+        return g, None
+
+
+def hierarchize_flat(u: torch.Tensor, levels_list) -> torch.Tensor:
+    levels = tuple(tuple(int(l) for l in lv) for lv in levels_list)
+    return HierarchizeFlat.apply(u, levels)

@@ -44,7 +44,8 @@ size_t esize_of(int dtype) { return dtype == SGH_F64 ? 8 : 4; }
 
 // ---------------------------------------------------------------------------
 // Validation (all or nothing).
-int validate_one(const sgh_grid &g, int idx, int64_t *npoints) {
+// relative: data holds a byte offset into a buffer given later (0 allowed).
+int validate_one(const sgh_grid &g, int idx, int64_t *npoints, bool relative = false) {
     if (g.dim < 1 || g.dim > SGH_MAX_DIM) return fail(SGH_ERR_ARG, "grid %d: dim %d outside 1..%d", idx, g.dim, SGH_MAX_DIM);
     if (g.dtype != SGH_F32 && g.dtype != SGH_F64) return fail(SGH_ERR_DTYPE, "grid %d: dtype %d", idx, g.dtype);
     // the product of 2^l_k - 1 must fit in int64 together with the element size
@@ -57,21 +58,21 @@ int validate_one(const sgh_grid &g, int idx, int64_t *npoints) {
     }
     if (log2n > 58.0) return fail(SGH_ERR_ARG, "grid %d: too many points (|l|_1 = %.0f)", idx, log2n);
     for (int k = 0; k < g.dim; ++k) n *= (int64_t(1) << g.level[k]) - 1;
-    if (g.data == nullptr) return fail(SGH_ERR_ARG, "grid %d: null data pointer", idx);
+    if (g.data == nullptr && !relative) return fail(SGH_ERR_ARG, "grid %d: null data pointer", idx);
     if (reinterpret_cast<uintptr_t>(g.data) % esize_of(g.dtype) != 0)
         return fail(SGH_ERR_ALIGN, "grid %d: data %p not aligned to %zu bytes", idx, g.data, esize_of(g.dtype));
     *npoints = n;
     return SGH_OK;
 }
 
-int validate_all(const sgh_grid *grids, int32_t n) {
+int validate_all(const sgh_grid *grids, int32_t n, bool relative = false) {
     if (n < 0) return fail(SGH_ERR_ARG, "negative grid count %d", n);
     if (n > 0 && grids == nullptr) return fail(SGH_ERR_ARG, "null grid array");
     std::vector<std::pair<uintptr_t, uintptr_t>> spans;
     spans.reserve(n);
     for (int i = 0; i < n; ++i) {
         int64_t np = 0;
-        int rc = validate_one(grids[i], i, &np);
+        int rc = validate_one(grids[i], i, &np, relative);
         if (rc) return rc;
         const uintptr_t b = reinterpret_cast<uintptr_t>(grids[i].data);
         spans.emplace_back(b, b + static_cast<uintptr_t>(np) * esize_of(grids[i].dtype));
@@ -834,6 +835,8 @@ struct BatchGroup {
     std::vector<int> grid_idx;  // into the plan's grid list, launch order (LPT)
     BatchTune tune;
     BatchTask *dev_tasks = nullptr;
+    int64_t max_bytes = 0;  // size class: grids of at most this many bytes (the LDS tile of its launch)
+    std::string suffix;     // timer name suffix of a size class ("" for a whole set)
 };
 
 struct PlanLarge {
@@ -857,6 +860,16 @@ int batch_lds_limit(int dtype) { return dtype == SGH_F64 ? 8192 * 8 : 16384 * 4;
 // as per-grid launches, which then run at full-chip bandwidth each.
 int64_t g_medium_max = int64_t(1) << 18;
 int g_medium_min = 16;
+
+// Size classes of the batch launch.  One launch sizes its workgroups and LDS
+// tile for its largest grid, so a set of grids of very different sizes runs
+// its small grids with mostly idle lanes and few workgroups per CU.  A set of
+// at least g_class_min_grids grids of one dtype is split into classes by LDS
+// bytes (up to 8, 16, 32, 64 KiB), one launch each; a class of fewer than
+// g_class_min_per grids joins the next larger one.  Smaller sets stay one
+// launch (each class launch would be too short to fill the GPU).
+int g_class_min_grids = 4096;
+int g_class_min_per = 1024;
 
 // Can one workgroup take grid g in passes through its tile?  Fills the task:
 // after the tile pass, runs of consecutive axes share one box pass while the
@@ -954,6 +967,7 @@ LaunchTimer::~LaunchTimer() { delete static_cast<TimerScope *>(impl_); }
 struct sgh_plan {
     int op = 0;
     uint32_t flags = 0;
+    bool relative = false;  // grid data fields are byte offsets into the buffer given at execute
     std::vector<sgh_grid> grids;
     std::vector<sgh::BatchGroup> groups;
     std::vector<sgh::MedGroup> medium;
@@ -990,23 +1004,38 @@ void fill_med_tasks(const sgh_plan &p, const MedGroup &mg, std::vector<MedTask> 
 
 std::string op_prefix(int op) { return op == 0 ? "hier" : op == 1 ? "dehier" : "adjoint"; }
 
-hipError_t plan_launch_all(sgh_plan *p, hipStream_t st) {
+// Every launch of a plan on `st`; base is null, or the buffer a relative
+// plan's offsets point into.
+hipError_t plan_launch_all(sgh_plan *p, hipStream_t st, const void *base = nullptr) {
     for (auto &bg : p->groups) {
-        TimerScope ts(op_prefix(p->op) + (bg.dtype == SGH_F64 ? "_f64" : "_f32") + "_batch", st);
+        TimerScope ts(op_prefix(p->op) + (bg.dtype == SGH_F64 ? "_f64" : "_f32") + "_batch" + bg.suffix, st);
         hipError_t e =
-            launch_batch(p->op, bg.dtype, bg.dev_tasks, static_cast<int32_t>(bg.grid_idx.size()), bg.tune, st);
+            launch_batch(p->op, bg.dtype, bg.dev_tasks, static_cast<int32_t>(bg.grid_idx.size()), bg.tune, base, st);
         if (e != hipSuccess) return e;
     }
     for (auto &mg : p->medium) {
         TimerScope ts(op_prefix(p->op) + (mg.dtype == SGH_F64 ? "_f64" : "_f32") + "_medium", st);
-        hipError_t e = launch_medium(p->op, mg.dtype, mg.dev_tasks, static_cast<int32_t>(mg.grid_idx.size()), st);
+        hipError_t e =
+            launch_medium(p->op, mg.dtype, mg.dev_tasks, static_cast<int32_t>(mg.grid_idx.size()), base, st);
         if (e != hipSuccess) return e;
     }
-    for (auto &lg : p->large)
+    for (auto &lg : p->large) {
+        if (base) {
+            // one-shot launches carry their grid's address: rebased copies
+            std::vector<Step> steps = lg.steps;
+            retarget(steps, static_cast<char *>(const_cast<void *>(base)) +
+                                reinterpret_cast<uintptr_t>(p->grids[lg.grid].data));
+            for (auto &s : steps) {
+                hipError_t e = run_step(p->op, lg.geom.dtype, s, st);
+                if (e != hipSuccess) return e;
+            }
+            continue;
+        }
         for (auto &s : lg.steps) {
             hipError_t e = run_step(p->op, lg.geom.dtype, s, st);
             if (e != hipSuccess) return e;
         }
+    }
     return hipSuccess;
 }
 
@@ -1067,7 +1096,8 @@ float time_median(F &&fn, hipStream_t st, int reps) {
 int autotune_group(sgh_plan *p, BatchGroup &bg) {
     const DevInfo &di = dev_info();
     std::ostringstream key;
-    key << di.arch << ":batch:op" << p->op << ":dt" << bg.dtype << ":n" << bg.grid_idx.size() << ":h";
+    key << di.arch << ":batch:op" << p->op << ":dt" << bg.dtype << ":n" << bg.grid_idx.size() << ":c" << bg.max_bytes
+        << ":h";
     uint64_t h = 1469598103934665603ull;
     int maxN = 0;
     int64_t total = 0;
@@ -1113,7 +1143,8 @@ int autotune_group(sgh_plan *p, BatchGroup &bg) {
                 if (persist && t.nwg == static_cast<int>(tasks.size())) continue;  // same launch as persist = 0
                 const float ms = time_median(
                     [&](hipStream_t s) {
-                        return launch_batch(p->op, bg.dtype, dtasks, static_cast<int32_t>(tasks.size()), t, s);
+                        return launch_batch(p->op, bg.dtype, dtasks, static_cast<int32_t>(tasks.size()), t,
+                                            nullptr, s);
                     },
                     st, 5);
                 if (ms < best) {
@@ -1373,12 +1404,16 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
     if (!plan) return fail(SGH_ERR_ARG, "null plan pointer");
     *plan = nullptr;
     if (op < 0 || op > 2) return fail(SGH_ERR_ARG, "unknown op %d", op);
-    int rc = validate_all(grids, n);
+    if (flags & ~(SGH_PLAN_GRAPH | SGH_PLAN_AUTOTUNE | SGH_PLAN_RELATIVE))
+        return fail(SGH_ERR_ARG, "unknown plan flags 0x%x", flags);
+    const bool relative = (flags & SGH_PLAN_RELATIVE) != 0;
+    int rc = validate_all(grids, n, relative);
     if (rc) return rc;
     std::unique_ptr<sgh_plan, void (*)(sgh_plan *)> p(new (std::nothrow) sgh_plan, plan_free);
     if (!p) return fail(SGH_ERR_NOMEM, "plan allocation");
     p->op = op;
     p->flags = flags;
+    p->relative = relative;
     p->grids.assign(grids, grids + n);
     const DevInfo &di = dev_info();
     // split: grids that fit one workgroup's LDS go to the batch kernel
@@ -1417,18 +1452,52 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
         lg.steps = build_schedule(op, lg.geom);
         p->large.push_back(lg);
     }
+    int class_min_grids, class_min_per;
+    {
+        std::lock_guard<std::mutex> lk(g_override_mu);
+        class_min_grids = g_class_min_grids;
+        class_min_per = g_class_min_per;
+    }
     for (auto &kv : small) {
-        BatchGroup bg;
-        bg.dtype = kv.first;
         auto v = kv.second;
+        const int dtype = kv.first;
+        const int64_t es = static_cast<int64_t>(esize_of(dtype));
         // longest processing time first; ties keep list order
         std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
-        for (auto &x : v) bg.grid_idx.push_back(x.second);
-        int maxN = static_cast<int>(v.front().first);
-        batch_default_tune(di, maxN, static_cast<int>(v.size()), bg.dtype, &bg.tune);
-        hipError_t e = hipMalloc(&bg.dev_tasks, v.size() * sizeof(BatchTask));
-        if (e != hipSuccess) return hip_fail(e, "task list");
-        p->groups.push_back(bg);
+        std::vector<std::pair<int64_t, std::vector<std::pair<int64_t, int>>>> classes;
+        if (class_min_grids > 0 && static_cast<int>(v.size()) >= class_min_grids) {
+            const int64_t bounds[] = {8192, 16384, 32768, 65536};
+            for (int64_t b : bounds) classes.push_back({b, {}});
+            for (auto &x : v) {
+                size_t c = 0;
+                while (x.first * es > classes[c].first) ++c;
+                classes[c].second.push_back(x);
+            }
+            // small classes join the next larger one (largest grids stay first)
+            for (size_t c = 0; c + 1 < classes.size(); ++c)
+                if (!classes[c].second.empty() && static_cast<int>(classes[c].second.size()) < class_min_per) {
+                    auto &nx = classes[c + 1].second;
+                    nx.insert(nx.end(), classes[c].second.begin(), classes[c].second.end());
+                    classes[c].second.clear();
+                }
+            // largest class first, so that its long grids start early
+            std::reverse(classes.begin(), classes.end());
+        } else {
+            classes.push_back({0, v});
+        }
+        for (auto &cl : classes) {
+            if (cl.second.empty()) continue;
+            BatchGroup bg;
+            bg.dtype = dtype;
+            bg.max_bytes = cl.first;
+            if (cl.first) bg.suffix = "_c" + std::to_string(cl.first / 1024) + "k";
+            for (auto &x : cl.second) bg.grid_idx.push_back(x.second);
+            const int maxN = static_cast<int>(cl.second.front().first);
+            batch_default_tune(di, maxN, static_cast<int>(cl.second.size()), bg.dtype, &bg.tune);
+            hipError_t e = hipMalloc(&bg.dev_tasks, cl.second.size() * sizeof(BatchTask));
+            if (e != hipSuccess) return hip_fail(e, "task list");
+            p->groups.push_back(bg);
+        }
     }
     if (flags & SGH_PLAN_AUTOTUNE) {
         for (auto &bg : p->groups) {
@@ -1451,7 +1520,7 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
     // slower than the launch it holds
     size_t launches = p->groups.size() + p->medium.size();
     for (const auto &lg : p->large) launches += lg.steps.size();
-    if ((flags & SGH_PLAN_GRAPH) && launches > 1) {
+    if ((flags & SGH_PLAN_GRAPH) && launches > 1 && !relative) {
         rc = plan_capture(p.get());
         if (rc) return rc;
     }
@@ -1462,6 +1531,7 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
 int sgh_plan_execute(sgh_plan *p, void *stream) {
     using namespace sgh;
     if (!p) return fail(SGH_ERR_ARG, "null plan");
+    if (p->relative) return fail(SGH_ERR_ARG, "a relative plan needs its buffer: sgh_plan_execute_at");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (p->exec) {
         TimerScope ts("graph", st);
@@ -1474,11 +1544,24 @@ int sgh_plan_execute(sgh_plan *p, void *stream) {
     return SGH_OK;
 }
 
+int sgh_plan_execute_at(sgh_plan *p, void *base, void *stream) {
+    using namespace sgh;
+    if (!p) return fail(SGH_ERR_ARG, "null plan");
+    if (!p->relative) return fail(SGH_ERR_ARG, "sgh_plan_execute_at needs a plan created with SGH_PLAN_RELATIVE");
+    if (!base) return fail(SGH_ERR_ARG, "null base");
+    for (const auto &g : p->grids)
+        if (reinterpret_cast<uintptr_t>(base) % esize_of(g.dtype) != 0)
+            return fail(SGH_ERR_ALIGN, "base %p not aligned to %zu bytes", base, esize_of(g.dtype));
+    hipError_t e = plan_launch_all(p, static_cast<hipStream_t>(stream), base);
+    if (e != hipSuccess) return hip_fail(e, "plan launch");
+    return SGH_OK;
+}
+
 int sgh_plan_set_data(sgh_plan *p, const sgh_grid *grids, int32_t n) {
     using namespace sgh;
     if (!p) return fail(SGH_ERR_ARG, "null plan");
     if (n != static_cast<int32_t>(p->grids.size())) return fail(SGH_ERR_ARG, "grid count %d != plan's %zu", n, p->grids.size());
-    int rc = validate_all(grids, n);
+    int rc = validate_all(grids, n, p->relative);
     if (rc) return rc;
     for (int i = 0; i < n; ++i) {
         const sgh_grid &a = p->grids[i], &b = grids[i];
@@ -1501,7 +1584,8 @@ int sgh_plan_describe(const sgh_plan *p, char *buf, int32_t len) {
     if (!p) return fail(SGH_ERR_ARG, "null plan");
     std::ostringstream ss;
     ss << "{\"op\":" << p->op << ",\"grids\":" << p->grids.size() << ",\"points\":" << p->points
-       << ",\"graph\":" << (p->exec ? "true" : "false") << ",\"batches\":[";
+       << ",\"graph\":" << (p->exec ? "true" : "false") << ",\"relative\":" << (p->relative ? "true" : "false")
+       << ",\"batches\":[";
     for (size_t i = 0; i < p->groups.size(); ++i) {
         const auto &bg = p->groups[i];
         if (i) ss << ",";
@@ -1510,7 +1594,7 @@ int sgh_plan_describe(const sgh_plan *p, char *buf, int32_t len) {
         ss << "{\"dtype\":" << bg.dtype << ",\"tasks\":" << bg.grid_idx.size() << ",\"points\":" << pts
            << ",\"nt\":" << bg.tune.nt
            << ",\"ept\":" << bg.tune.ept << ",\"workgroups\":" << bg.tune.nwg << ",\"lds_bytes\":" << bg.tune.lds_bytes
-           << ",\"persistent\":" << bg.tune.persist
+           << ",\"persistent\":" << bg.tune.persist << ",\"class_bytes\":" << bg.max_bytes
            << "}";
     }
     ss << "],\"medium\":[";
@@ -1597,6 +1681,16 @@ int sgh_set_medium_limits(int64_t max_points, int32_t min_grids) {
     std::lock_guard<std::mutex> lk(g_override_mu);
     g_medium_max = max_points;
     g_medium_min = min_grids;
+    return SGH_OK;
+}
+
+int sgh_set_batch_classes(int32_t min_grids, int32_t min_per_class) {
+    using namespace sgh;
+    if (min_grids < 0 || min_per_class < 1)
+        return fail(SGH_ERR_ARG, "batch class limits %d, %d outside >= 0, >= 1", min_grids, min_per_class);
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    g_class_min_grids = min_grids;
+    g_class_min_per = min_per_class;
     return SGH_OK;
 }
 

@@ -192,9 +192,10 @@ struct BatchTune {
     hipError_t launch_tw_##SUF(const TWLaunch &p, hipStream_t s);                                     \
     hipError_t launch_split_##SUF(const SplitLaunch &p, hipStream_t s);                               \
     hipError_t launch_box_##SUF(const BoxLaunch &p, const TileTune &t, hipStream_t s);                \
-    hipError_t launch_medium_##SUF(const MedTask *dev_tasks, int32_t ntasks, hipStream_t s);          \
+    hipError_t launch_medium_##SUF(const MedTask *dev_tasks, int32_t ntasks, const void *base,        \
+                                   hipStream_t s);                                                    \
     hipError_t launch_batch_##SUF(const BatchTask *dev_tasks, int32_t ntasks, const BatchTune &t,    \
-                                  hipStream_t s);
+                                  const void *base, hipStream_t s);
 SGH_DECLARE_LAUNCHERS(f64_h)
 SGH_DECLARE_LAUNCHERS(f64_d)
 SGH_DECLARE_LAUNCHERS(f64_a)
@@ -230,12 +231,15 @@ inline hipError_t launch_split(int op, int dtype, const SplitLaunch &p, hipStrea
 inline hipError_t launch_box(int op, int dtype, const BoxLaunch &p, const TileTune &t, hipStream_t s) {
     SGH_ROUTE(launch_box, p, t, s);
 }
-inline hipError_t launch_medium(int op, int dtype, const MedTask *dev_tasks, int32_t ntasks, hipStream_t s) {
-    SGH_ROUTE(launch_medium, dev_tasks, ntasks, s);
+// Batch and medium task lists hold grid addresses relative to `base` (null:
+// absolute device addresses).
+inline hipError_t launch_medium(int op, int dtype, const MedTask *dev_tasks, int32_t ntasks, const void *base,
+                                hipStream_t s) {
+    SGH_ROUTE(launch_medium, dev_tasks, ntasks, base, s);
 }
 inline hipError_t launch_batch(int op, int dtype, const BatchTask *dev_tasks, int32_t ntasks, const BatchTune &t,
-                               hipStream_t s) {
-    SGH_ROUTE(launch_batch, dev_tasks, ntasks, t, s);
+                               const void *base, hipStream_t s) {
+    SGH_ROUTE(launch_batch, dev_tasks, ntasks, t, base, s);
 }
 #undef SGH_ROUTE
 

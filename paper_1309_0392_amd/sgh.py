@@ -21,7 +21,7 @@ MAX_DIM = 16
 MAX_LEVEL = 30
 F32, F64 = 0, 1
 OP_HIERARCHIZE, OP_DEHIERARCHIZE, OP_ADJOINT = 0, 1, 2
-PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
+PLAN_GRAPH, PLAN_AUTOTUNE, PLAN_RELATIVE = 1, 2, 4
 
 OK = 0
 ERR_ARG, ERR_DTYPE, ERR_ALIGN, ERR_OVERLAP, ERR_HIP, ERR_NOMEM, ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
@@ -66,6 +66,8 @@ def lib():
             "sgh_transform": ([i32, G, i32, vp], ctypes.c_int),
             "sgh_plan_create": ([ctypes.POINTER(vp), i32, G, i32, u32], ctypes.c_int),
             "sgh_plan_execute": ([vp, vp], ctypes.c_int),
+            "sgh_plan_execute_at": ([vp, vp, vp], ctypes.c_int),
+            "sgh_set_batch_classes": ([i32, i32], ctypes.c_int),
             "sgh_plan_set_data": ([vp, G, i32], ctypes.c_int),
             "sgh_plan_describe": ([vp, ctypes.c_char_p, i32], ctypes.c_int),
             "sgh_plan_destroy": ([vp], None),
@@ -250,6 +252,72 @@ class Plan:
             pass
 
 
+class FlatPlan:
+    """A relative plan (SGH_PLAN_RELATIVE) over a set of grids stored back to
+    back, in list order, in one flat tensor of `total` elements: grid i is the
+    slice [starts[i], starts[i] + size_i).  The tensor is named at each
+    execution, so one plan serves every buffer of that layout."""
+
+    def __init__(self, op: int, levels_list, dtype: int, autotune: bool = False):
+        self.op = op
+        self.levels = [tuple(int(x) for x in l) for l in levels_list]
+        self.n = len(self.levels)
+        self.dtype = int(dtype)
+        esize = 8 if self.dtype == F64 else 4
+        self.sizes = [int(np_prod((1 << l) - 1 for l in lv)) for lv in self.levels]
+        self.starts = []
+        off = 0
+        for sz in self.sizes:
+            self.starts.append(off)
+            off += sz
+        self.total = off
+        descs = [make_grid(lv, self.dtype, 0) for lv in self.levels]
+        for g, st in zip(descs, self.starts):
+            g.data = ctypes.c_void_p(st * esize) if st else None
+        self._arr = grid_array(descs)
+        handle = ctypes.c_void_p()
+        flags = PLAN_RELATIVE | (PLAN_AUTOTUNE if autotune else 0)
+        _check(lib().sgh_plan_create(ctypes.byref(handle), op, self._arr, self.n, flags), "sgh_plan_create")
+        self._h = handle
+
+    def views(self, flat):
+        """The grids of a flat tensor, as views of their shapes."""
+        return [flat[a:a + n].view(shape_of(lv)) for a, n, lv in zip(self.starts, self.sizes, self.levels)]
+
+    def execute(self, flat, stream=None):
+        import torch
+        want = torch.float64 if self.dtype == F64 else torch.float32
+        if flat.dtype != want or not flat.is_cuda or not flat.is_contiguous() or flat.numel() != self.total:
+            raise ValueError("flat buffer must be a contiguous %s device tensor of %d elements" % (want, self.total))
+        _check(lib().sgh_plan_execute_at(self._h, ctypes.c_void_p(flat.data_ptr()), _stream_handle(stream)),
+               "sgh_plan_execute_at")
+        return flat
+
+    def describe(self) -> dict:
+        need = lib().sgh_plan_describe(self._h, None, 0)
+        buf = ctypes.create_string_buffer(max(need, 1))
+        lib().sgh_plan_describe(self._h, buf, len(buf))
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().sgh_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def np_prod(values) -> int:
+    p = 1
+    for v in values:
+        p *= int(v)
+    return p
+
+
 # ------------------------------------------------------ combination technique
 class Combination:
     """The sparse grid of a combination set (sgh_combi_*): gather of the grids'
@@ -383,6 +451,12 @@ def set_split_spans(fine: int = 0, coarse: int = 0):
 def set_box_limits(max_bytes: int = 0, min_row_bytes: int = 0):
     """Size limits of the launches that transform runs of small strided axes together (0 = default)."""
     _check(lib().sgh_set_box_limits(int(max_bytes), int(min_row_bytes)), "sgh_set_box_limits")
+
+
+def set_batch_classes(min_grids: int = 4096, min_per_class: int = 1024):
+    """Plans: split the small grids of one dtype into size classes (one batch launch each) when there
+    are at least min_grids of them (0 = never); classes below min_per_class grids join the next one."""
+    _check(lib().sgh_set_batch_classes(int(min_grids), int(min_per_class)), "sgh_set_batch_classes")
 
 
 def set_medium_limits(max_points: int = 1 << 18, min_grids: int = 16):

@@ -36,6 +36,7 @@ def test_header_constants_match_binding():
     assert int(consts["SGH_F32"]) == sgh.F32 and int(consts["SGH_F64"]) == sgh.F64
     assert int(consts["SGH_ERR_OVERLAP"]) == sgh.ERR_OVERLAP
     assert int(consts["SGH_PLAN_GRAPH"].rstrip("u")) == sgh.PLAN_GRAPH
+    assert int(consts["SGH_PLAN_RELATIVE"].rstrip("u")) == sgh.PLAN_RELATIVE
     # struct layout: dim, level[16], dtype, data pointer
     assert ctypes.sizeof(sgh.SghGrid) == 80 and sgh.SghGrid.data.offset == 72
 
@@ -228,6 +229,20 @@ def test_fusion_switch():
     finally:
         sgh.set_fusion(1)
         sgh.set_pole_split(9, 0, 0, 0)
+
+
+def test_batch_classes_knob():
+    sgh.set_batch_classes(0, 1)
+    sgh.set_batch_classes(10, 5)
+    sgh.set_batch_classes()
+    for bad in ((-1, 1), (4096, 0)):
+        with pytest.raises(sgh.SghError):
+            sgh.set_batch_classes(*bad)
+
+
+def test_plain_descriptor_may_not_be_null():
+    # (a relative plan's offsets may be 0; plain descriptors need a pointer)
+    assert sgh.validate([sgh.make_grid((5, 5), sgh.F64, 0)]) == sgh.ERR_ARG
 
 
 def test_medium_limits_knob():

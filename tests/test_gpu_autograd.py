@@ -68,3 +68,35 @@ def test_combination_loss_gradient_fp32():
         fd = (lp - lm) / h
         assert abs(fd - refs[g].ravel()[flat]) <= 1e-9 * gmax
         assert abs(fd - grads[g].ravel()[flat]) <= 1e-5 * gmax, (g, flat)
+
+
+def test_flat_set_gradcheck():
+    lv = [(2, 3), (3,), (2, 2, 2), (1, 2)]
+    n = sum(W.num_points(l) for l in lv)
+    u = torch.from_numpy(np.random.default_rng(6).uniform(-1, 1, n)).cuda().requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda v: AG.hierarchize_flat(v, lv), (u,), eps=1e-6, atol=1e-10)
+
+
+def test_combination_loss_gradient_flat_fp32():
+    """The same loss on the set stored back to back in one FP32 tensor: the
+    forward equals the per-grid oracle, the gradient 2 c_l H^T H u_l."""
+    lv, coef = W.combination_set()
+    xs = W.combination_values(lv, seed=3, dtype=np.float32)
+    flat = np.concatenate([x.ravel() for x in xs])
+    w = np.concatenate([np.full(x.size, c, dtype=np.float32) for x, c in zip(xs, coef)])
+    u = torch.from_numpy(flat).cuda().requires_grad_(True)
+    y = AG.hierarchize_flat(u, lv)
+    loss = (torch.from_numpy(w).cuda().double() * y.double() ** 2).sum()
+    (g,) = torch.autograd.grad(loss, u)
+    plan = AG.flat_plan(0, tuple(tuple(l) for l in lv), torch.float32, u.device)
+    assert plan.total == flat.size and plan.describe()["relative"] is True
+    ys = [t.detach().cpu().numpy().astype(np.float64) for t in plan.views(y)]
+    gs = [t.cpu().numpy().astype(np.float64) for t in plan.views(g)]
+    hs = [oracle.hierarchize(x.astype(np.float64), l) for x, l in zip(xs, lv)]
+    xmax = max(float(np.abs(x).max()) for x in xs)
+    assert max(float(np.max(np.abs(a - b))) for a, b in zip(ys, hs)) <= 2e-6 * xmax
+    refs = [2.0 * c * oracle.hierarchize_adjoint(h, l) for h, l, c in zip(hs, lv, coef)]
+    gmax = max(float(np.max(np.abs(r))) for r in refs)
+    err = max(float(np.max(np.abs(a - b))) for a, b in zip(gs, refs)) / gmax
+    print("FP32 flat gradient vs FP64 oracle: %.3e" % err, flush=True)
+    assert err <= 2e-6

@@ -5,15 +5,17 @@ into the sparse grid, scatter back into the grids, and the reduce step
 Gather sums the grids' coefficient-weighted values in list order with products
 and sums rounded separately, as the oracle does, so FP64 gather is compared
 bitwise; scatter only copies, so it is bitwise in both dtypes.  The reduce step
-goes through the hierarchization kernels and is compared within the transform
-tolerances (FP64 1e-14, FP32 storage 2e-6 of the FP64 oracle on the upcast
-inputs), scaled by the largest input magnitude times the sum of |coefficients|
-for the sparse surpluses."""
+goes through the hierarchization kernels and is compared point by point within
+bounds built from each point's own contributors (tests/combi_bounds.py): the
+transform tolerances (FP64 1e-14, FP32 storage 2e-6 of the FP64 oracle on the
+upcast inputs) weighted by the point's |coefficients|, the rounding of its
+weighted sum, and, for grid points, the propagation through the inverse."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
+from combi_bounds import reduce_bounds, reduce_violations
 from paper_1309_0392_amd import sgh
 from paper_1309_0392_amd import workloads as W
 
@@ -84,22 +86,19 @@ def test_scatter_matches_oracle(name, dtype):
 
 
 def _check_reduce(xs, levels, coefs, ts, sp, dtype):
-    """Error scales from the arithmetic: a surplus is at most 2^d max|x| in
-    magnitude (each axis subtracts the mean of two values), so the partial sums
-    of coef * surplus over the grids stay below 2^d max|x| sum|c|, and the
-    sparse surpluses are held to TOL of that; a nodal value after the scatter
-    sums at most prod_k l_k surpluses with hat weights <= 1, plus its own
-    rounding."""
-    ref_grids, ref_sp = oracle.combi_round_trip([x.astype(np.float64) for x in xs], levels, coefs)
-    xmax = max(float(max(np.abs(x).max() for x in xs)), 1e-300)
-    csum = sum(abs(v) for v in coefs)
-    sp_tol = TOL[dtype] * 2 ** len(levels[0]) * xmax * csum
+    """Every sparse point and every grid point within its own bound, from the
+    point's actual contributors (tests/combi_bounds.py)."""
+    x64 = [x.astype(np.float64) for x in xs]
+    ref_grids, ref_sp = oracle.combi_round_trip(x64, levels, coefs)
+    sp_tol, grid_tol = reduce_bounds(x64, levels, coefs, dtype, ref_grids)
     got_sp = sp.cpu().numpy().astype(np.float64)
-    assert np.max(np.abs(got_sp - ref_sp)) <= sp_tol
-    for g, (got, ref, lv) in enumerate(zip(_host(ts), ref_grids, levels)):
-        tol = sp_tol * float(np.prod(lv)) + TOL[dtype] * max(float(np.abs(ref).max()), xmax)
-        err = np.max(np.abs(got.astype(np.float64) - ref))
-        assert err <= tol, "grid %d: %g > %g" % (g, err, tol)
+    got = _host(ts)
+    worst_sp = float(np.max(np.abs(got_sp - ref_sp) / sp_tol)) if sp_tol.size else 0.0
+    worst_g = max((float(np.max(np.abs(g.astype(np.float64) - r) / t)) for g, r, t in zip(got, ref_grids, grid_tol)
+                   if r.size), default=0.0)
+    print("reduce %s: worst error / bound: sparse %.3f, grids %.3f" % (np.dtype(dtype).name, worst_sp, worst_g),
+          flush=True)
+    assert reduce_violations(got_sp, got, ref_sp, ref_grids, sp_tol, grid_tol) == (0, 0)
 
 
 @pytest.mark.parametrize("name", list(SETS))

@@ -1,16 +1,15 @@
 """The workloads at full size on the GPU, checked against the oracle.
 
-Full-size grids (1 GB) are too large to run the whole oracle in a test; there
-the check is on sampled output points (computed one by one by the oracle's
-per-point routines) plus the round trip dehierarchize(hierarchize(x)) = x over
-every element.  The combination-technique batch (589 grids) is checked grid by
-grid against the whole-grid oracle."""
+The full-size grids (about 1 GB each) are compared with the whole-grid oracle
+on every element, for every operation and element type, plus the round trip
+dehierarchize(hierarchize(x)) = x.  The combination-technique batch (589
+grids) is checked grid by grid against the whole-grid oracle."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
-from gpu_util import OP_NAME, ORACLE, TOL, gpu_run, rel_err
+from gpu_util import OP_NAME, ORACLE, TOL, gpu_run, rel_err, scale_of
 from paper_1309_0392_amd import sgh
 from paper_1309_0392_amd import workloads as W
 
@@ -36,36 +35,45 @@ def test_small_2d_round_trip():
 
 @pytest.mark.parametrize("name", ["aniso3d", "aniso5d"])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
-def test_full_size_sampled(name, dtype):
+def test_full_size_every_element(name, dtype):
+    """The benchmark grids at full size, in the launch configuration bench.py
+    times, against the whole-grid oracle on every element, for all three
+    operations (a sampled pre-check of 300 points comes first, so that a gross
+    error names itself quickly)."""
     if name == "aniso3d":
         levels, x = W.ANISO_3D, W.sine_plus_noise(W.ANISO_3D, seed=1)
     else:
         levels, x = W.ANISO_5D, W.uniform(W.ANISO_5D, seed=2)
     x = x.astype(dtype)
     x64 = x.astype(np.float64)
-    pos = sample_positions(levels, 3000, seed=17)
+    xmax = float(np.max(np.abs(x64)))
+    pos = sample_positions(levels, 300, seed=17)
+    idx = tuple((pos[:, k] - 1) for k in reversed(range(len(levels))))
     dev = torch.from_numpy(x).cuda()
-    print("full size %s %s: %d points" % (name, dtype.__name__, dev.numel()), flush=True)
+    print("full size %s %s: %d points" % (name, np.dtype(dtype).name, dev.numel()), flush=True)
     for op in (sgh.OP_HIERARCHIZE, sgh.OP_ADJOINT, sgh.OP_DEHIERARCHIZE):
+        sched = [l["kind"] for l in sgh.schedule(op, levels, sgh.F64 if dtype == np.float64 else sgh.F32)["launches"]]
         t = dev.clone()
         sgh.transform(op, t, levels)
         torch.cuda.synchronize()
         got = t.cpu().numpy()
-        idx = tuple((pos[:, k] - 1) for k in reversed(range(len(levels))))
-        ref = oracle.point(OP_NAME[op] if op != sgh.OP_ADJOINT else "adjoint", x64, levels, pos)
-        scale = float(np.max(np.abs(x64)))
-        if op != sgh.OP_HIERARCHIZE:
-            scale = max(scale, float(np.max(np.abs(ref))))
-        err = float(np.max(np.abs(got[idx].astype(np.float64) - ref))) / scale
-        print("  %s sampled err %.3e" % (OP_NAME[op], err), flush=True)
-        assert err <= TOL[dtype]
         del t
+        pre = oracle.point(OP_NAME[op], x64, levels, pos)
+        pre_err = float(np.max(np.abs(got[idx].astype(np.float64) - pre))) / scale_of(op, x64, pre)
+        assert pre_err <= TOL[dtype], (OP_NAME[op], "sampled", pre_err)
+        ref = ORACLE[op](x64, levels)
+        err = rel_err(op, x64, got, ref)
+        err_in = float(np.max(np.abs(got.astype(np.float64) - ref))) / xmax
+        print("  %s %s: max error / scale %.3e, / max|x| %.3e" % (OP_NAME[op], "+".join(sched), err, err_in),
+              flush=True)
+        assert err <= TOL[dtype], (OP_NAME[op], err)
+        del got, ref
     # round trip over every element
     t = dev.clone()
     sgh.hierarchize(t, levels)
     sgh.dehierarchize(t, levels)
     torch.cuda.synchronize()
-    rt = float(torch.max(torch.abs(t - dev)).item()) / float(np.max(np.abs(x64)))
+    rt = float(torch.max(torch.abs(t - dev)).item()) / xmax
     print("  round trip err %.3e" % rt, flush=True)
     assert rt <= (1e-14 if dtype == np.float64 else 4e-6)
 
@@ -163,3 +171,61 @@ def test_autotuned_plan_matches():
     for t, x, l in zip(ts, xs, lv):
         assert rel_err(0, x.astype(np.float64), t.cpu().numpy(), oracle.hierarchize(x.astype(np.float64), l)) <= 2e-6
     plan.close()
+
+
+def test_flat_plan_equals_plan_and_rebases():
+    """A relative plan gives the plan's results bit for bit, on two different
+    buffers of the same layout (no re-upload between them)."""
+    lv, _, xs = combi(np.float64)
+    lv = lv + [(10, 9, 4), (7, 7)]  # plus grids beyond the tile (one-shot launches, rebased per call)
+    xs = xs + [W.uniform(l, [41, i]) for i, l in enumerate(lv[-2:])]
+    ts = [torch.from_numpy(x.copy()).cuda() for x in xs]
+    for op in ORACLE:
+        plan = sgh.Plan(op, ts, lv, graph=False)
+        flat = sgh.FlatPlan(op, lv, sgh.F64)
+        for t, x in zip(ts, xs):
+            t.copy_(torch.from_numpy(x))
+        plan.execute()
+        for rep in range(2):
+            buf = torch.empty(flat.total + 64 * rep, dtype=torch.float64, device="cuda")[64 * rep:]
+            for v, x in zip(flat.views(buf), xs):
+                v.copy_(torch.from_numpy(x))
+            flat.execute(buf)
+            torch.cuda.synchronize()
+            for a, b in zip(flat.views(buf), ts):
+                assert torch.equal(a, b), OP_NAME[op]
+        # a relative plan refuses the plain execute
+        assert sgh.lib().sgh_plan_execute(flat._h, None) == sgh.ERR_ARG
+        plan.close()
+        flat.close()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_size_classes_bitwise_equal_to_one_launch(dtype):
+    """Size-classed batch launches apply the same per-point updates as one
+    launch: results equal bit for bit, and equal the oracle within tolerance."""
+    lv, _, xs = combi(dtype)
+    ts1 = [torch.from_numpy(x.copy()).cuda() for x in xs]
+    ts2 = [torch.from_numpy(x.copy()).cuda() for x in xs]
+    try:
+        for op in ORACLE:
+            sgh.set_batch_classes(0, 1)
+            p1 = sgh.Plan(op, ts1, lv, graph=False)
+            sgh.set_batch_classes(1, 1)
+            p2 = sgh.Plan(op, ts2, lv, graph=False)
+            assert len(p1.describe()["batches"]) == 1 and len(p2.describe()["batches"]) == 4
+            for t1, t2, x in zip(ts1, ts2, xs):
+                t1.copy_(torch.from_numpy(x))
+                t2.copy_(torch.from_numpy(x))
+            p1.execute()
+            p2.execute()
+            torch.cuda.synchronize()
+            for t1, t2, x, l in zip(ts1, ts2, xs, lv):
+                assert torch.equal(t1, t2), (OP_NAME[op], l)
+            worst = max(rel_err(op, x.astype(np.float64), t.cpu().numpy(), ORACLE[op](x.astype(np.float64), l))
+                        for t, x, l in zip(ts2, xs, lv))
+            assert worst <= TOL[dtype]
+            p1.close()
+            p2.close()
+    finally:
+        sgh.set_batch_classes()

@@ -1,8 +1,8 @@
 """The largest cases the library accepts, against the oracle: the top level
 (30, a 4 GiB FP32 pole), a 2 GiB FP64 pole, and the maximum dimension (16 axes
 of 3 points, 43 M points).  FP64 results are compared bitwise (the split and
-tile paths keep the oracle's per-point order); the FP32 level-30 pole on sampled
-points (each computed on its own by the oracle) and by its round trip."""
+tile paths keep the oracle's per-point order); the FP32 level-30 pole on every
+element against the FP64 oracle on the upcast input, and by its round trip."""
 import numpy as np
 import pytest
 import torch
@@ -16,6 +16,7 @@ pytestmark = pytest.mark.gpu
 
 
 def test_top_level_pole_f32():
+    # the level-30 FP32 pole (4 GiB) against the whole-pole FP64 oracle on every element
     levels = (sgh.MAX_LEVEL,)
     N = (1 << 30) - 1
     gen = torch.Generator(device="cuda")
@@ -25,13 +26,16 @@ def test_top_level_pole_f32():
     print("level-30 FP32 pole (4 GiB)", flush=True)
     sgh.hierarchize(x, levels)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(71)
-    pos = np.concatenate([[1, 2, 3, N, N - 1, 1 << 29, (1 << 29) + 1, 1 << 12, (1 << 12) + 1, 3 << 12],
-                          rng.integers(1, N + 1, size=40)]).reshape(-1, 1)
     xin = x0.cpu().numpy().astype(np.float64)
-    ref = oracle.point("hierarchize", xin, levels, pos)
-    got = x[torch.from_numpy(pos[:, 0] - 1).cuda()].cpu().numpy().astype(np.float64)
-    assert np.max(np.abs(got - ref)) <= TOL[np.float32] * np.abs(xin).max()
+    xmax = float(np.abs(xin).max())
+    ref = oracle.hierarchize(xin, levels)
+    got = x.cpu().numpy()
+    err = 0.0
+    for a in range(0, N, 1 << 27):  # in slices, to bound the temporaries
+        err = max(err, float(np.max(np.abs(got[a:a + (1 << 27)].astype(np.float64) - ref[a:a + (1 << 27)]))))
+    del ref, got
+    print("  max error / max|x| %.3e" % (err / xmax), flush=True)
+    assert err <= TOL[np.float32] * xmax
     sgh.dehierarchize(x, levels)
     torch.cuda.synchronize()
     # a nodal value sums at most 30 surpluses, each within the FP32 rounding of the forward pass
