@@ -287,6 +287,24 @@ int sgh_set_batch_classes(int32_t min_grids, int32_t min_per_class);
  * the same map.  Applies to schedules and plans built after the call. */
 int sgh_set_fusion(int32_t level);
 
+/* Schedule switch for hierarchization: 1 (default) folds the axis right
+ * after a fused launch's walked axis into that launch.  Along an axis the
+ * hierarchization is a one-shot stencil on nodal values (Algorithm 1 reads
+ * each point's predecessors before they change), and the axes commute, so a
+ * pencil that is one plane of that axis is first combined, as its rows are
+ * read, with the same rows of its two hierarchical predecessor planes
+ * (x - a/2 - b/2), then transformed along the tile and walked axes: one HBM
+ * write per point for all of these axes; the predecessor rows are read
+ * again by other workgroups at about the same time and mostly come from the
+ * caches.  0 keeps a separate launch for that axis.  Applies to schedules
+ * and plans built after the call. */
+int sgh_set_outer_stencil(int32_t on);
+
+/* Launch-order switch for fused launches: 1 deals consecutive pencils to one
+ * XCD (its L2 then holds the rows that neighbouring pencils share), 0
+ * (default) keeps the hardware's round-robin order. */
+int sgh_set_xcd_order(int32_t on);
+
 /* Which strided axis the fused launch walks when several qualify and no
  * autotuned choice exists: 0 (default) the one with the smallest stride (each
  * workgroup then streams one contiguous slab), 1 the one with the largest. */

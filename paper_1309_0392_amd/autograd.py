@@ -93,26 +93,50 @@ def flat_plan(op: int, levels: Tuple[Tuple[int, ...], ...], dtype: torch.dtype, 
     return plan
 
 
+class FlatSet:
+    """A combination set stored back to back, in list order, in one flat tensor
+    (grid i at starts[i]), with the relative plans of its hierarchization and
+    of its adjoint built once: a forward and backward then cost two plan
+    executions and two copies, however many grids the set holds."""
+
+    def __init__(self, levels_list, dtype: torch.dtype = torch.float32, device=None):
+        self.levels = tuple(tuple(int(l) for l in lv) for lv in levels_list)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.dtype = dtype
+        self.fwd = flat_plan(sgh.OP_HIERARCHIZE, self.levels, dtype, self.device)
+        self.adj = flat_plan(sgh.OP_ADJOINT, self.levels, dtype, self.device)
+        self.total = self.fwd.total
+        self.starts = self.fwd.starts
+
+    def views(self, flat: torch.Tensor) -> List[torch.Tensor]:
+        return self.fwd.views(flat)
+
+    def hierarchize(self, u: torch.Tensor) -> torch.Tensor:
+        return HierarchizeFlat.apply(u, self)
+
+
 class HierarchizeFlat(torch.autograd.Function):
-    """A combination set held back to back in one flat tensor (grid i at
-    FlatPlan.starts[i]): forward hierarchizes a copy, backward applies the
-    adjoint kernels to a copy of the incoming gradient, each as the launches of
-    one relative plan (no task-list upload, no synchronization)."""
+    """A combination set held back to back in one flat tensor: forward
+    hierarchizes a copy, backward applies the adjoint kernels to a copy of the
+    incoming gradient, each as the launches of one relative plan (no task-list
+    upload, no synchronization)."""
 
     @staticmethod
-    def forward(ctx, u: torch.Tensor, levels: Tuple[Tuple[int, ...], ...]):
-        ctx.levels = levels
+    def forward(ctx, u: torch.Tensor, fs: "FlatSet"):
+        ctx.fs = fs
         y = u.detach().contiguous().clone()
-        flat_plan(sgh.OP_HIERARCHIZE, levels, y.dtype, y.device).execute(y)
+        fs.fwd.execute(y)
         return y
 
     @staticmethod
     def backward(ctx, grad_y: torch.Tensor):
         g = grad_y.detach().contiguous().clone()
-        flat_plan(sgh.OP_ADJOINT, ctx.levels, g.dtype, g.device).execute(g)
+        ctx.fs.adj.execute(g)
         return g, None
 
 
 def hierarchize_flat(u: torch.Tensor, levels_list) -> torch.Tensor:
-    levels = tuple(tuple(int(l) for l in lv) for lv in levels_list)
-    return HierarchizeFlat.apply(u, levels)
+    """y = H u for a set stored back to back in u; `levels_list` is a list of
+    level vectors or a FlatSet (which skips the per-call plan lookup)."""
+    fs = levels_list if isinstance(levels_list, FlatSet) else FlatSet(levels_list, u.dtype, u.device)
+    return HierarchizeFlat.apply(u, fs)

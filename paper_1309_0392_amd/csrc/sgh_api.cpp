@@ -292,6 +292,8 @@ int g_split_fine = 0;    // block span exponent of the first split phase, 0 = la
 int g_box_bytes = 0;     // largest box launch tile in bytes, 0 = default
 int g_box_row = 0;       // smallest box row (columns * element size) in bytes, 0 = default
 int g_split_coarse = 0;  // the same for the later phases, 0 = default
+int g_outer_stencil = 1; // hierarchization: fold the axis after a three-level walk into the fused launch
+int g_tw_xcd = 0;        // fused launches: consecutive pencils on one XCD
 
 int pole_B_override(int L) {
     std::lock_guard<std::mutex> lk(g_override_mu);
@@ -366,6 +368,7 @@ std::string grid_key(int op, const Geom &g) {
 struct SchedOpts {
     int walk = -1;
     bool walk_two_level = false;  // force the two-level walk in the fused kernel
+    int outer = -1;               // fold the next axis into a three-level walk: -1 knob, 0 no, 1 yes
     int tile_mult = 0;
     std::vector<int> pole_code;
 };
@@ -521,7 +524,7 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
     const int64_t cap = tile_capacity(g.dtype);
     int64_t Sm = 1;
     int m = tile_axes(g, &Sm);
-    int walk = -1;
+    int walk = -1, folded = -1;
     if (m >= 1 && m < g.d && fusion_level() >= 1 && o.walk != -2) {
         if (o.walk >= 0 && walk_ok(g, m, Sm, o.walk)) {
             walk = o.walk;
@@ -559,6 +562,20 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
             s.tw.B = 3;
         }
         s.tw.g = make_tile_geom(g, m);
+        int outer = 0;
+        {
+            std::lock_guard<std::mutex> lk(g_override_mu);
+            outer = o.outer >= 0 ? o.outer : g_outer_stencil;
+            s.tw.xcd = g_tw_xcd;
+        }
+        if (op == SGH_OP_HIERARCHIZE && s.tw.split == 3 && outer && walk + 1 < g.d) {
+            // the next axis's one-shot stencil is applied as the pencil's rows are read
+            s.tw.oL = g.L[walk + 1];
+            s.tw.on = static_cast<int32_t>(g.n[walk + 1]);
+            s.axes.push_back(walk + 1);
+            s.key = walk + 1;
+            folded = walk + 1;
+        }
         steps.push_back(s);
     } else if (m >= 1) {
         Step s;
@@ -581,14 +598,15 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
         m = 1;
     }
     for (int k = m; k < g.d; ++k) {
-        if (k == walk) continue;
+        if (k == walk || k == folded) continue;
         if (fusion_level() >= 1) {
             // consecutive small strided axes: one box launch for all of them
             const BoxLimits lim = box_limits();
             const int es = g.dtype == SGH_F64 ? 8 : 4;
             int kend = k, W = box_width(g.n[k], es, lim);
             int64_t P = g.n[k];
-            while (kend + 1 < g.d && kend + 1 != walk && box_width(P * g.n[kend + 1], es, lim) > 0) {
+            while (kend + 1 < g.d && kend + 1 != walk && kend + 1 != folded &&
+                   box_width(P * g.n[kend + 1], es, lim) > 0) {
                 P *= g.n[++kend];
                 W = box_width(P, es, lim);
             }
@@ -719,7 +737,10 @@ std::string step_timer_name(int op, int dtype, const Step &s) {
     ss << ops[op] << "_" << (dtype == SGH_F64 ? "f64" : "f32") << "_" << step_name(s);
     if (s.kind == Step::POLE) ss << "_L" << s.pole.L;
     if (s.kind == Step::TILE) ss << "_m" << s.tile.g.m;
-    if (s.kind == Step::TW) ss << "_m" << s.tw.g.m << "_L" << s.tw.L;
+    if (s.kind == Step::TW) {
+        ss << "_m" << s.tw.g.m << "_L" << s.tw.L;
+        if (s.tw.oL) ss << "_o" << s.tw.oL;
+    }
     if (s.kind == Step::SPLIT) ss << "_L" << s.split.L << "_E" << s.split.E;
     if (s.kind == Step::BOX) ss << "_m" << s.box.g.m;
     return ss.str();
@@ -741,6 +762,7 @@ bool step_launchable(const Step &s) {
             return s.pole.split == 3 ? pole3_supported(s.pole.L, s.pole.TB, s.pole.B) && s.ptune.nt == 256
                                      : pole_supported(s.pole.L, s.pole.B);
         case Step::TW:
+            if (s.tw.oL > 0 && s.tw.split != 3) return false;
             return s.tw.split == 3 ? s.tw.ept == 1 && tw3_supported(s.tw.L, s.tw.TB, s.tw.B)
                                    : tw_supported(s.tw.L, s.tw.B, s.tw.ept);
         case Step::SPLIT:
@@ -785,7 +807,8 @@ std::string describe_steps(int op, const Geom &g, const std::vector<Step> &steps
                << ",\"ept\":" << s.ttune.ept;
         if (s.kind == Step::TW)
             ss << ",\"L\":" << s.tw.L << ",\"B\":" << s.tw.B << ",\"split\":" << s.tw.split << ",\"TB\":" << s.tw.TB
-               << ",\"ept\":" << s.tw.ept << ",\"tile\":" << s.tw.Sm << ",\"workgroups\":" << s.tw.nwg;
+               << ",\"ept\":" << s.tw.ept << ",\"tile\":" << s.tw.Sm << ",\"workgroups\":" << s.tw.nwg
+               << ",\"outer_level\":" << s.tw.oL << ",\"xcd_order\":" << s.tw.xcd;
         ss << "}";
         // the coarse split phases touch a small part of the grid
         trips += (s.kind == Step::SPLIT && s.split.E > 0) ? 0 : 1;
@@ -1691,6 +1714,22 @@ int sgh_set_batch_classes(int32_t min_grids, int32_t min_per_class) {
     std::lock_guard<std::mutex> lk(g_override_mu);
     g_class_min_grids = min_grids;
     g_class_min_per = min_per_class;
+    return SGH_OK;
+}
+
+int sgh_set_outer_stencil(int32_t on) {
+    using namespace sgh;
+    if (on < 0 || on > 1) return fail(SGH_ERR_ARG, "outer stencil switch %d outside 0..1", on);
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    g_outer_stencil = on;
+    return SGH_OK;
+}
+
+int sgh_set_xcd_order(int32_t on) {
+    using namespace sgh;
+    if (on < 0 || on > 1) return fail(SGH_ERR_ARG, "XCD order switch %d outside 0..1", on);
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    g_tw_xcd = on;
     return SGH_OK;
 }
 

@@ -121,6 +121,13 @@ struct TWLaunch {
     int32_t ept;  // tile elements per thread (threads = 1024)
     int32_t split = 2;  // 2: two-level walk; 3: three-level walk (L = TB + 2B, ept 1)
     int32_t TB = 0;
+    // Hierarchization with the three-level walk only: the axis right after the
+    // walked one (stride n * Sw, level oL, on = 2^oL - 1 points) is transformed
+    // in the same pass by its one-shot stencil, applied as the rows are read
+    // (oL = 0: off).
+    int32_t oL = 0;
+    int32_t on = 0;
+    int32_t xcd = 0;  // 1: consecutive pencils on one XCD (workgroup order)
     TileGeom g;   // tile axes
 };
 

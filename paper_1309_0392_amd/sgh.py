@@ -68,6 +68,8 @@ def lib():
             "sgh_plan_execute": ([vp, vp], ctypes.c_int),
             "sgh_plan_execute_at": ([vp, vp, vp], ctypes.c_int),
             "sgh_set_batch_classes": ([i32, i32], ctypes.c_int),
+            "sgh_set_outer_stencil": ([i32], ctypes.c_int),
+            "sgh_set_xcd_order": ([i32], ctypes.c_int),
             "sgh_plan_set_data": ([vp, G, i32], ctypes.c_int),
             "sgh_plan_describe": ([vp, ctypes.c_char_p, i32], ctypes.c_int),
             "sgh_plan_destroy": ([vp], None),
@@ -457,6 +459,16 @@ def set_batch_classes(min_grids: int = 4096, min_per_class: int = 1024):
     """Plans: split the small grids of one dtype into size classes (one batch launch each) when there
     are at least min_grids of them (0 = never); classes below min_per_class grids join the next one."""
     _check(lib().sgh_set_batch_classes(int(min_grids), int(min_per_class)), "sgh_set_batch_classes")
+
+
+def set_outer_stencil(on: int = 1):
+    """Hierarchization: fold the axis after a fused three-level walk into that launch (1, default) or not (0)."""
+    _check(lib().sgh_set_outer_stencil(int(on)), "sgh_set_outer_stencil")
+
+
+def set_xcd_order(on: int = 0):
+    """Fused launches: deal consecutive pencils to one XCD (1) or keep the hardware order (0, default)."""
+    _check(lib().sgh_set_xcd_order(int(on)), "sgh_set_xcd_order")
 
 
 def set_medium_limits(max_points: int = 1 << 18, min_grids: int = 16):

@@ -93,15 +93,34 @@ def test_num_points():
 
 
 def test_schedules():
+    # hierarchization: axis 0 in an LDS tile fused with axis 1 walked in
+    # registers (each workgroup streams one contiguous plane), and axis 2's
+    # one-shot stencil applied as the plane's rows are read: one launch
     s = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D)
-    kinds = [(l["kind"], tuple(l["axes"])) for l in s["launches"]]
-    # axis 0 in an LDS tile fused with axis 1 walked in registers (each workgroup
-    # streams one contiguous plane); axis 2 strided
-    assert kinds == [("tw", (0, 1)), ("pole", (2,))]
-    assert [l.get("L") for l in s["launches"]] == [9, 8]
-    assert [(l["split"], l["TB"], l["B"]) for l in s["launches"]] == [(3, 3, 3), (3, 2, 3)]
-    assert s["launches"][1]["prefetch"] == 1
-    assert s["hbm_round_trips"] == 2
+    assert [(l["kind"], tuple(l["axes"])) for l in s["launches"]] == [("tw", (0, 1, 2))]
+    assert (s["launches"][0]["L"], s["launches"][0]["outer_level"]) == (9, 8)
+    assert s["hbm_round_trips"] == 1
+    try:
+        sgh.set_outer_stencil(0)
+        s = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D)
+        kinds = [(l["kind"], tuple(l["axes"])) for l in s["launches"]]
+        # axis 2 in its own strided launch
+        assert kinds == [("tw", (0, 1)), ("pole", (2,))]
+        assert [l.get("L") for l in s["launches"]] == [9, 8]
+        assert [(l["split"], l["TB"], l["B"]) for l in s["launches"]] == [(3, 3, 3), (3, 2, 3)]
+        assert s["launches"][1]["prefetch"] == 1
+        assert s["hbm_round_trips"] == 2
+    finally:
+        sgh.set_outer_stencil(1)
+    with pytest.raises(sgh.SghError):
+        sgh.set_outer_stencil(2)
+    # only the hierarchization has the one-shot stencil; a two-level walk folds nothing
+    for lv in ((10, 9, 8), (10, 7, 3, 2), (9, 8, 5)):
+        for op in (sgh.OP_DEHIERARCHIZE, sgh.OP_ADJOINT):
+            assert all(l.get("outer_level", 0) == 0 for l in sgh.schedule(op, lv)["launches"])
+    assert [tuple(l["axes"]) for l in sgh.schedule(sgh.OP_HIERARCHIZE, (10, 7, 3, 2))["launches"]] == [
+        (0, 1, 2), (3,)]
+    assert sgh.schedule(sgh.OP_HIERARCHIZE, (10, 4, 8))["launches"][0]["outer_level"] == 0
     d = sgh.schedule(sgh.OP_DEHIERARCHIZE, W.ANISO_3D)
     assert [tuple(l["axes"]) for l in d["launches"]] == [(2,), (0, 1)]
     s5 = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_5D)
@@ -168,7 +187,7 @@ def test_box_schedules():
         assert all(l["box"] * 8 <= 16384 and l["W"] * 8 >= 256 for l in s["launches"] if l["kind"] == "box")
     finally:
         sgh.set_box_limits(0, 0)
-    assert [l["kind"] for l in sgh.schedule(sgh.OP_HIERARCHIZE, (10, 9, 8))["launches"]] == ["tw", "pole"]
+    assert [l["kind"] for l in sgh.schedule(sgh.OP_DEHIERARCHIZE, (10, 9, 8))["launches"]] == ["pole", "tw"]
     # FP32 rows of 16 columns are too short to pair the two level-5 axes of (6,6,5,5,5)
     s = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_5D, sgh.F32)
     assert [l["kind"] for l in s["launches"]] == ["tw", "pole", "pole"]

@@ -256,3 +256,38 @@ def test_shape_checks_in_binding():
         sgh.hierarchize(t.t(), (5, 5))
     with pytest.raises(TypeError):
         sgh.hierarchize(t.half(), (5, 5))
+
+
+FOLDED = [(10, 7, 3), (10, 8, 2), (9, 9, 4), (10, 9, 1, 3), (10, 7, 5, 2), (8, 7, 6), (3, 3, 9, 5), (7, 8, 7)]
+
+
+@pytest.mark.parametrize("levels", FOLDED, ids=ids)
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_folded_outer_axis(levels, dtype):
+    """Hierarchization with the axis after a three-level walk folded into the
+    fused launch (its one-shot stencil applied as the rows are read): against
+    the oracle, against the schedule with that axis in its own launch, and with
+    the pencils dealt to XCDs in runs (bit for bit the same arithmetic)."""
+    code = sgh.F64 if dtype == np.float64 else sgh.F32
+    sched = sgh.schedule(sgh.OP_HIERARCHIZE, levels, code)
+    tw = sched["launches"][0]
+    assert tw["kind"] == "tw" and tw["split"] == 3 and tw["outer_level"] > 0, sched
+    x = W.uniform(levels, [29, len(levels)], dtype)
+    x64 = x.astype(np.float64)
+    ref = oracle.hierarchize(x64, levels)
+    got = gpu_run(sgh.OP_HIERARCHIZE, x, levels)
+    err = rel_err(sgh.OP_HIERARCHIZE, x64, got, ref)
+    print("folded levels=%s %s: err %.3e" % (levels, np.dtype(dtype).name, err), flush=True)
+    assert err <= TOL[dtype]
+    try:
+        sgh.set_xcd_order(1)
+        assert sgh.schedule(sgh.OP_HIERARCHIZE, levels, code)["launches"][0]["xcd_order"] == 1
+        np.testing.assert_array_equal(gpu_run(sgh.OP_HIERARCHIZE, x, levels), got)
+        sgh.set_xcd_order(0)
+        sgh.set_outer_stencil(0)
+        assert sgh.schedule(sgh.OP_HIERARCHIZE, levels, code)["launches"][0]["outer_level"] == 0
+        unfolded = gpu_run(sgh.OP_HIERARCHIZE, x, levels)
+        assert float(np.max(np.abs(unfolded.astype(np.float64) - got))) <= 2 * TOL[dtype] * np.abs(x64).max()
+    finally:
+        sgh.set_xcd_order(0)
+        sgh.set_outer_stencil(1)
