@@ -301,6 +301,7 @@ def run_grid(args, torch, np, sgh, W, name):
     }
     out["timing_protocol"] = protocol(torch, step, lambda: sgh.dehierarchize(x, levels))
     out["timing_protocol"]["points_per_s_median"] = N / (out["timing_protocol"]["forward"]["median_ms"] * 1e-3)
+    out["out_of_place"] = out_of_place(args, torch, sgh, x, levels, code, algo, name if dt == "f64" else name + "_f32")
 
     if not args.no_extras:
         extras = {}
@@ -342,6 +343,27 @@ def run_grid(args, torch, np, sgh, W, name):
         del work, x64
     out["input_generation_s"] = gen_s
     return out
+
+
+def out_of_place(args, torch, sgh, x, levels, code, algo, workload):
+    """The same grid transformed out of place (sgh_transform_out) into a second
+    resident buffer: hierarchization (whose fused launch also takes the next
+    axis), and the inverse and transpose of the result."""
+    N = x.numel()
+    y = torch.empty_like(x)
+    res = {}
+    for nm, op in (("hierarchize", sgh.OP_HIERARCHIZE), ("dehierarchize", sgh.OP_DEHIERARCHIZE),
+                   ("adjoint", sgh.OP_ADJOINT)):
+        f = lambda op=op: sgh.transform_out(op, x, y, levels)
+        for _ in range(args.warmup):
+            f()
+        ms, rep = timed_kernels(torch, sgh, f, args.steps)
+        res[nm] = {"points_per_s": N / (ms * 1e-3), "ms": ms, "kernels": kernel_table(rep, lambda k: algo),
+                   "schedule": sgh.schedule(op, levels, code, out_of_place=True)["launches"],
+                   "hbm_round_trips": sgh.schedule(op, levels, code, out_of_place=True)["hbm_round_trips"],
+                   "roofline": roofline_of(rep, lambda k: algo, workload + "_out")}
+    del y
+    return res
 
 
 def batch_extras(torch, np, sgh, W):

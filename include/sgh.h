@@ -95,6 +95,18 @@ int sgh_hierarchize_adjoint(const sgh_grid *grids, int32_t n, void *stream);
 /* Same as the three above, selected by op (SGH_OP_*). */
 int sgh_transform(int32_t op, const sgh_grid *grids, int32_t n, void *stream);
 
+/* Out of place: dst[i] receives op applied to src[i], which is left
+ * unchanged.  src[i] and dst[i] have the same dim, levels and dtype; no
+ * destination may overlap any source or another destination, except that
+ * dst[i].data == src[i].data is allowed and means in place for that grid
+ * (SGH_ERR_OVERLAP otherwise; SGH_ERR_ARG for differing shapes).  The first
+ * launch of each grid's schedule reads the source and writes the
+ * destination, so the result costs no more HBM traffic than in place; for
+ * the hierarchization a fused launch also takes the axis after its walked
+ * axis (its one-shot stencil reads the predecessor planes, which stay nodal
+ * in the source), one HBM round trip fewer than in place. */
+int sgh_transform_out(int32_t op, const sgh_grid *src, const sgh_grid *dst, int32_t n, void *stream);
+
 /* ---- batched plans ------------------------------------------------------
  *
  * A plan fixes an operation and a list of grids (shapes, dtypes and data
@@ -145,6 +157,11 @@ int sgh_plan_execute(sgh_plan *plan, void *stream);
  * sgh_plan_execute.  SGH_ERR_ARG for a plan created without the flag or a
  * null base, SGH_ERR_ALIGN for a misaligned base. */
 int sgh_plan_execute_at(sgh_plan *plan, void *base, void *stream);
+/* A relative plan out of place: the grids at src_base + offset are
+ * transformed into dst_base + offset (the source is left unchanged).  The
+ * two buffers must not overlap over the plan's extent (SGH_ERR_OVERLAP);
+ * equal bases mean in place.  Allocates nothing. */
+int sgh_plan_execute_out(sgh_plan *plan, const void *src_base, void *dst_base, void *stream);
 /* Repoint the plan to new buffers of identical shapes and dtypes (same n,
  * same order).  Synchronizes the device first (an execute in flight may still
  * read the old task list), then rewrites the device task list; the graph is
@@ -222,8 +239,10 @@ int64_t sgh_num_points(const sgh_grid *grid);
  * subspace count S to *num_subspaces and the total points to *points. */
 int sgh_sparse_layout(const sgh_grid *grids, int32_t n, int32_t capacity, int32_t *sub_levels, int64_t *offsets,
                       int32_t *num_subspaces, int64_t *points);
-/* Describes the launch schedule the library would use for one grid (JSON). */
+/* Describes the launch schedule the library would use for one grid (JSON),
+ * in place and out of place (sgh_transform_out). */
 int sgh_schedule_describe(int32_t op, const sgh_grid *grid, char *buf, int32_t len);
+int sgh_schedule_describe_out(int32_t op, const sgh_grid *grid, char *buf, int32_t len);
 const char *sgh_error_string(int code);
 const char *sgh_last_error_message(void);
 /* Library version, e.g. "0.1.0". */
@@ -287,17 +306,19 @@ int sgh_set_batch_classes(int32_t min_grids, int32_t min_per_class);
  * the same map.  Applies to schedules and plans built after the call. */
 int sgh_set_fusion(int32_t level);
 
-/* Schedule switch for hierarchization: 1 (default) folds the axis right
- * after a fused launch's walked axis into that launch.  Along an axis the
- * hierarchization is a one-shot stencil on nodal values (Algorithm 1 reads
- * each point's predecessors before they change), and the axes commute, so a
- * pencil that is one plane of that axis is first combined, as its rows are
- * read, with the same rows of its two hierarchical predecessor planes
- * (x - a/2 - b/2), then transformed along the tile and walked axes: one HBM
- * write per point for all of these axes; the predecessor rows are read
- * again by other workgroups at about the same time and mostly come from the
- * caches.  0 keeps a separate launch for that axis.  Applies to schedules
- * and plans built after the call. */
+/* Schedule switch for out-of-place hierarchization (sgh_transform_out,
+ * sgh_plan_execute_out): 1 (default) folds the axis right after a fused
+ * launch's walked axis into that launch.  Along an axis the hierarchization
+ * is a one-shot stencil on nodal values (Algorithm 1 reads each point's
+ * predecessors before they change), and the axes commute, so a pencil that
+ * is one plane of that axis is first combined, as its rows are read, with
+ * the same rows of its two hierarchical predecessor planes (x - a/2 - b/2),
+ * then transformed along the tile and walked axes: one HBM write per point
+ * for all of these axes; the predecessor rows are read again by other
+ * workgroups at about the same time and mostly come from the caches.  In
+ * place this is never done (the predecessor planes would be overwritten
+ * while they are read).  0 keeps a separate launch for that axis.  Applies
+ * to schedules and plans built after the call. */
 int sgh_set_outer_stencil(int32_t on);
 
 /* Launch-order switch for fused launches: 1 deals consecutive pencils to one

@@ -5,9 +5,10 @@
     ys = hierarchize_batch(us, levels_list)    # a combination-grid set, one plan
     y = hierarchize_flat(u, levels_list)       # a set stored back to back in one tensor
 
-Both are out of place (the input is cloned, then transformed in place on the
-GPU).  The backward of y = H u is  grad_u = H^T grad_y,  computed by the
-library's adjoint kernels on a clone of grad_y.
+All are out of place: hierarchize and hierarchize_flat read the input and write
+a new tensor (the library's out-of-place launches); hierarchize_batch clones,
+then transforms the clones in place.  The backward of y = H u is
+grad_u = H^T grad_y,  computed by the library's adjoint kernels.
 """
 from __future__ import annotations
 
@@ -22,14 +23,16 @@ class Hierarchize(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u: torch.Tensor, levels: Tuple[int, ...]):
         ctx.levels = tuple(int(l) for l in levels)
-        y = u.detach().contiguous().clone()
-        sgh.hierarchize(y, ctx.levels)
+        u = u.detach().contiguous()
+        y = torch.empty_like(u)
+        sgh.transform_out(sgh.OP_HIERARCHIZE, u, y, ctx.levels)
         return y
 
     @staticmethod
     def backward(ctx, grad_y: torch.Tensor):
-        g = grad_y.detach().contiguous().clone()
-        sgh.hierarchize_adjoint(g, ctx.levels)
+        gy = grad_y.detach().contiguous()
+        g = torch.empty_like(gy)
+        sgh.transform_out(sgh.OP_ADJOINT, gy, g, ctx.levels)
         return g, None
 
 
@@ -97,7 +100,7 @@ class FlatSet:
     """A combination set stored back to back, in list order, in one flat tensor
     (grid i at starts[i]), with the relative plans of its hierarchization and
     of its adjoint built once: a forward and backward then cost two plan
-    executions and two copies, however many grids the set holds."""
+    executions, however many grids the set holds."""
 
     def __init__(self, levels_list, dtype: torch.dtype = torch.float32, device=None):
         self.levels = tuple(tuple(int(l) for l in lv) for lv in levels_list)
@@ -116,22 +119,24 @@ class FlatSet:
 
 
 class HierarchizeFlat(torch.autograd.Function):
-    """A combination set held back to back in one flat tensor: forward
-    hierarchizes a copy, backward applies the adjoint kernels to a copy of the
-    incoming gradient, each as the launches of one relative plan (no task-list
-    upload, no synchronization)."""
+    """A combination set held back to back in one flat tensor: forward writes
+    the hierarchized set into a new tensor, backward the adjoint of the
+    incoming gradient, each as the out-of-place launches of one relative plan
+    (no copy, no task-list upload, no synchronization)."""
 
     @staticmethod
     def forward(ctx, u: torch.Tensor, fs: "FlatSet"):
         ctx.fs = fs
-        y = u.detach().contiguous().clone()
-        fs.fwd.execute(y)
+        u = u.detach().contiguous()
+        y = torch.empty_like(u)
+        fs.fwd.execute_out(u, y)
         return y
 
     @staticmethod
     def backward(ctx, grad_y: torch.Tensor):
-        g = grad_y.detach().contiguous().clone()
-        ctx.fs.adj.execute(g)
+        gy = grad_y.detach().contiguous()
+        g = torch.empty_like(gy)
+        ctx.fs.adj.execute_out(gy, g)
         return g, None
 
 

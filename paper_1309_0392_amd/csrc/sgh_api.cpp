@@ -369,6 +369,7 @@ struct SchedOpts {
     int walk = -1;
     bool walk_two_level = false;  // force the two-level walk in the fused kernel
     int outer = -1;               // fold the next axis into a three-level walk: -1 knob, 0 no, 1 yes
+    bool oop = false;             // out-of-place schedule (its first launch reads the source grid)
     int tile_mult = 0;
     std::vector<int> pole_code;
 };
@@ -568,8 +569,10 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
             outer = o.outer >= 0 ? o.outer : g_outer_stencil;
             s.tw.xcd = g_tw_xcd;
         }
-        if (op == SGH_OP_HIERARCHIZE && s.tw.split == 3 && outer && walk + 1 < g.d) {
-            // the next axis's one-shot stencil is applied as the pencil's rows are read
+        if (o.oop && op == SGH_OP_HIERARCHIZE && s.tw.split == 3 && outer && walk + 1 < g.d) {
+            // the next axis's one-shot stencil is applied as the pencil's rows are
+            // read (out of place only: the predecessor planes are read while
+            // other workgroups transform them)
             s.tw.oL = g.L[walk + 1];
             s.tw.on = static_cast<int32_t>(g.n[walk + 1]);
             s.axes.push_back(walk + 1);
@@ -704,21 +707,24 @@ std::vector<Step> build_schedule_opts(int op, const Geom &g, const SchedOpts &o)
 }
 
 // The schedule the library uses: autotuned choices when cached, else defaults.
-std::vector<Step> build_schedule(int op, const Geom &g) {
+std::vector<Step> build_schedule(int op, const Geom &g, bool oop = false) {
     std::vector<int> tuned;
     SchedOpts o;
     if (tune_get(grid_key(op, g), &tuned)) o = opts_from_tuned(g, tuned);
+    o.oop = oop;
     return build_schedule_opts(op, g, o);
 }
 
+void retarget_one(Step &s, void *data) {
+    s.tile.data = data;
+    s.pole.data = data;
+    s.tw.data = data;
+    s.split.data = data;
+    s.box.data = data;
+}
+
 void retarget(std::vector<Step> &steps, void *data) {
-    for (auto &s : steps) {
-        s.tile.data = data;
-        s.pole.data = data;
-        s.tw.data = data;
-        s.split.data = data;
-        s.box.data = data;
-    }
+    for (auto &s : steps) retarget_one(s, data);
 }
 
 const char *step_name(const Step &s) {
@@ -783,6 +789,36 @@ hipError_t run_step(int op, int dtype, const Step &s, hipStream_t st) {
         case Step::BOX: return launch_box(op, dtype, s.box, s.ttune, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// A schedule run out of place: the first launch reads src and writes dst
+// (pole and fused launches take a destination), every later one works on dst
+// in place; a schedule that starts with another kind of launch copies src to
+// dst first.
+hipError_t run_schedule_out(int op, int dtype, const std::vector<Step> &steps, void *src, void *dst, size_t bytes,
+                            hipStream_t st) {
+    size_t i0 = 0;
+    if (!steps.empty() && (steps[0].kind == Step::TW || steps[0].kind == Step::POLE)) {
+        Step f = steps[0];
+        retarget_one(f, src);
+        f.tw.dst = dst;
+        f.pole.dst = dst;
+        hipError_t e = run_step(op, dtype, f, st);
+        if (e != hipSuccess) return e;
+        i0 = 1;
+    } else if (bytes) {
+        hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    for (size_t i = i0; i < steps.size(); ++i) {
+        Step s = steps[i];
+        retarget_one(s, dst);
+        s.tw.dst = nullptr;
+        s.pole.dst = nullptr;
+        hipError_t e = run_step(op, dtype, s, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 std::string describe_steps(int op, const Geom &g, const std::vector<Step> &steps) {
@@ -851,6 +887,58 @@ int transform(int op, const sgh_grid *grids, int32_t n, void *stream) {
     return SGH_OK;
 }
 
+// Out of place: grid i of dst receives the transform of grid i of src (same
+// shape and dtype); dst grids overlap no src grid and no other dst grid,
+// except that dst[i] may be src[i] itself (then in place).
+int transform_out(int op, const sgh_grid *src, const sgh_grid *dst, int32_t n, void *stream) {
+    if (op < 0 || op > 2) return fail(SGH_ERR_ARG, "unknown op %d", op);
+    int rc = validate_all(src, n);
+    if (rc) return rc;
+    rc = validate_all(dst, n);
+    if (rc) return rc;
+    std::vector<std::pair<uintptr_t, uintptr_t>> sspan, dspan;
+    for (int i = 0; i < n; ++i) {
+        const sgh_grid &a = src[i], &b = dst[i];
+        bool same = a.dim == b.dim && a.dtype == b.dtype;
+        for (int k = 0; same && k < a.dim; ++k) same = a.level[k] == b.level[k];
+        if (!same) return fail(SGH_ERR_ARG, "grid %d: source and destination differ in shape or dtype", i);
+        const uintptr_t bytes = static_cast<uintptr_t>(make_geom(a).N) * esize_of(a.dtype);
+        sspan.emplace_back(reinterpret_cast<uintptr_t>(a.data), reinterpret_cast<uintptr_t>(a.data) + bytes);
+        dspan.emplace_back(reinterpret_cast<uintptr_t>(b.data), reinterpret_cast<uintptr_t>(b.data) + bytes);
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            if (i == j && dspan[i].first == sspan[j].first) continue;  // in place
+            if (dspan[i].first < sspan[j].second && sspan[j].first < dspan[i].second)
+                return fail(SGH_ERR_OVERLAP, "destination %d overlaps source %d", i, j);
+        }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<std::vector<Step>> all(static_cast<size_t>(n));
+    for (int i = 0; i < n; ++i) {
+        const bool inplace = dspan[i].first == sspan[i].first;
+        all[static_cast<size_t>(i)] = build_schedule(op, make_geom(src[i]), !inplace);
+        for (auto &s : all[static_cast<size_t>(i)])
+            if (!step_launchable(s))
+                return fail(SGH_ERR_UNSUPPORTED, "grid %d: no %s kernel for this shape under the current tuning knobs", i,
+                            step_name(s));
+    }
+    for (int i = 0; i < n; ++i) {
+        hipError_t e;
+        if (dspan[i].first == sspan[i].first) {
+            e = hipSuccess;
+            for (auto &s : all[static_cast<size_t>(i)]) {
+                e = run_step(op, src[i].dtype, s, st);
+                if (e != hipSuccess) break;
+            }
+        } else {
+            e = run_schedule_out(op, src[i].dtype, all[static_cast<size_t>(i)], src[i].data, dst[i].data,
+                                 dspan[i].second - dspan[i].first, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    }
+    return SGH_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Batched plans.
 struct BatchGroup {
@@ -866,6 +954,7 @@ struct PlanLarge {
     int grid = 0;
     Geom geom;
     std::vector<Step> steps;
+    std::vector<Step> steps_out;  // relative plans: the out-of-place schedule
 };
 
 // Grids of a plan too large for one LDS tile but small enough that one
@@ -991,6 +1080,7 @@ struct sgh_plan {
     int op = 0;
     uint32_t flags = 0;
     bool relative = false;  // grid data fields are byte offsets into the buffer given at execute
+    int64_t extent = 0;     // relative plans: bytes from offset 0 to the end of the last grid
     std::vector<sgh_grid> grids;
     std::vector<sgh::BatchGroup> groups;
     std::vector<sgh::MedGroup> medium;
@@ -1027,13 +1117,55 @@ void fill_med_tasks(const sgh_plan &p, const MedGroup &mg, std::vector<MedTask> 
 
 std::string op_prefix(int op) { return op == 0 ? "hier" : op == 1 ? "dehier" : "adjoint"; }
 
+// A relative plan out of place: the grids at src + offset are transformed into
+// dst + offset.  The batch launches read src and write dst; with medium grids
+// the whole extent is copied first and those run in place on dst; large grids
+// run their out-of-place schedules.
+hipError_t plan_launch_out(sgh_plan *p, hipStream_t st, const void *src, void *dst) {
+    if (!p->medium.empty()) {
+        hipError_t e = hipMemcpyAsync(dst, src, static_cast<size_t>(p->extent), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    for (auto &bg : p->groups) {
+        TimerScope ts(op_prefix(p->op) + (bg.dtype == SGH_F64 ? "_f64" : "_f32") + "_batch" + bg.suffix, st);
+        hipError_t e = launch_batch(p->op, bg.dtype, bg.dev_tasks, static_cast<int32_t>(bg.grid_idx.size()), bg.tune,
+                                    src, dst, st);
+        if (e != hipSuccess) return e;
+    }
+    for (auto &mg : p->medium) {
+        TimerScope ts(op_prefix(p->op) + (mg.dtype == SGH_F64 ? "_f64" : "_f32") + "_medium", st);
+        hipError_t e =
+            launch_medium(p->op, mg.dtype, mg.dev_tasks, static_cast<int32_t>(mg.grid_idx.size()), dst, st);
+        if (e != hipSuccess) return e;
+    }
+    for (auto &lg : p->large) {
+        const uintptr_t off = reinterpret_cast<uintptr_t>(p->grids[lg.grid].data);
+        char *d = static_cast<char *>(dst) + off;
+        hipError_t e;
+        if (p->medium.empty()) {
+            e = run_schedule_out(p->op, lg.geom.dtype, lg.steps_out, const_cast<char *>(static_cast<const char *>(src)) + off,
+                                 d, static_cast<size_t>(lg.geom.N) * esize_of(lg.geom.dtype), st);
+        } else {
+            std::vector<Step> steps = lg.steps;  // already copied: in place on dst
+            retarget(steps, d);
+            e = hipSuccess;
+            for (auto &s : steps) {
+                e = run_step(p->op, lg.geom.dtype, s, st);
+                if (e != hipSuccess) break;
+            }
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Every launch of a plan on `st`; base is null, or the buffer a relative
 // plan's offsets point into.
 hipError_t plan_launch_all(sgh_plan *p, hipStream_t st, const void *base = nullptr) {
     for (auto &bg : p->groups) {
         TimerScope ts(op_prefix(p->op) + (bg.dtype == SGH_F64 ? "_f64" : "_f32") + "_batch" + bg.suffix, st);
-        hipError_t e =
-            launch_batch(p->op, bg.dtype, bg.dev_tasks, static_cast<int32_t>(bg.grid_idx.size()), bg.tune, base, st);
+        hipError_t e = launch_batch(p->op, bg.dtype, bg.dev_tasks, static_cast<int32_t>(bg.grid_idx.size()), bg.tune,
+                                    base, base, st);
         if (e != hipSuccess) return e;
     }
     for (auto &mg : p->medium) {
@@ -1167,7 +1299,7 @@ int autotune_group(sgh_plan *p, BatchGroup &bg) {
                 const float ms = time_median(
                     [&](hipStream_t s) {
                         return launch_batch(p->op, bg.dtype, dtasks, static_cast<int32_t>(tasks.size()), t,
-                                            nullptr, s);
+                                            nullptr, nullptr, s);
                     },
                     st, 5);
                 if (ms < best) {
@@ -1199,6 +1331,7 @@ int autotune_large(sgh_plan *p, PlanLarge &lg) {
     std::vector<int> cached;
     if (tune_get(key, &cached)) {
         lg.steps = build_schedule(p->op, lg.geom);
+        if (p->relative) lg.steps_out = build_schedule(p->op, lg.geom, true);
         return SGH_OK;
     }
     const size_t es = esize_of(lg.geom.dtype);
@@ -1320,6 +1453,7 @@ int autotune_large(sgh_plan *p, PlanLarge &lg) {
     if (e != hipSuccess) return hip_fail(e, "autotune");
     tune_put(key, tuned_from_opts(lg.geom, best_opts));
     lg.steps = build_schedule(p->op, lg.geom);
+    if (p->relative) lg.steps_out = build_schedule(p->op, lg.geom, true);
     return SGH_OK;
 }
 
@@ -1382,6 +1516,10 @@ int sgh_transform(int32_t op, const sgh_grid *grids, int32_t n, void *stream) {
     return sgh::transform(op, grids, n, stream);
 }
 
+int sgh_transform_out(int32_t op, const sgh_grid *src, const sgh_grid *dst, int32_t n, void *stream) {
+    return sgh::transform_out(op, src, dst, n, stream);
+}
+
 int sgh_validate(const sgh_grid *grids, int32_t n) { return sgh::validate_all(grids, n); }
 
 int64_t sgh_num_points(const sgh_grid *grid) {
@@ -1402,6 +1540,17 @@ int sgh_schedule_describe(int32_t op, const sgh_grid *grid, char *buf, int32_t l
     if (rc) return rc;
     sgh::Geom ge = sgh::make_geom(g);
     return sgh::copy_out(sgh::describe_steps(op, ge, sgh::build_schedule(op, ge)), buf, len);
+}
+
+int sgh_schedule_describe_out(int32_t op, const sgh_grid *grid, char *buf, int32_t len) {
+    if (!grid || op < 0 || op > 2) return sgh::fail(SGH_ERR_ARG, "bad arguments");
+    sgh_grid g = *grid;
+    if (g.data == nullptr) g.data = reinterpret_cast<void *>(uintptr_t(256));
+    int64_t np = 0;
+    int rc = sgh::validate_one(g, 0, &np);
+    if (rc) return rc;
+    sgh::Geom ge = sgh::make_geom(g);
+    return sgh::copy_out(sgh::describe_steps(op, ge, sgh::build_schedule(op, ge, true)), buf, len);
 }
 
 const char *sgh_error_string(int code) {
@@ -1445,6 +1594,9 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
     for (int i = 0; i < n; ++i) {
         Geom g = make_geom(grids[i]);
         p->points += g.N;
+        if (relative)
+            p->extent = std::max<int64_t>(p->extent, static_cast<int64_t>(reinterpret_cast<uintptr_t>(grids[i].data)) +
+                                                         g.N * static_cast<int64_t>(esize_of(g.dtype)));
         if (g.d == 0) continue;  // all axes of level 1: identity
         if (g.N * static_cast<int64_t>(esize_of(g.dtype)) <= batch_lds_limit(g.dtype))
             small[g.dtype].push_back({g.N, i});
@@ -1473,6 +1625,7 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
         lg.grid = i;
         lg.geom = make_geom(grids[i]);
         lg.steps = build_schedule(op, lg.geom);
+        if (relative) lg.steps_out = build_schedule(op, lg.geom, true);
         p->large.push_back(lg);
     }
     int class_min_grids, class_min_per;
@@ -1533,8 +1686,9 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
         }
     }
     for (const auto &lg : p->large)
-        for (const auto &s : lg.steps)
-            if (!step_launchable(s))
+        for (const auto *v : {&lg.steps, &lg.steps_out})
+            for (const auto &s : *v)
+                if (!step_launchable(s))
                 return fail(SGH_ERR_UNSUPPORTED, "grid %d: no %s kernel for this shape under the current tuning knobs",
                             lg.grid, step_name(s));
     rc = plan_upload(p.get());
@@ -1576,6 +1730,28 @@ int sgh_plan_execute_at(sgh_plan *p, void *base, void *stream) {
         if (reinterpret_cast<uintptr_t>(base) % esize_of(g.dtype) != 0)
             return fail(SGH_ERR_ALIGN, "base %p not aligned to %zu bytes", base, esize_of(g.dtype));
     hipError_t e = plan_launch_all(p, static_cast<hipStream_t>(stream), base);
+    if (e != hipSuccess) return hip_fail(e, "plan launch");
+    return SGH_OK;
+}
+
+int sgh_plan_execute_out(sgh_plan *p, const void *src_base, void *dst_base, void *stream) {
+    using namespace sgh;
+    if (!p) return fail(SGH_ERR_ARG, "null plan");
+    if (!p->relative) return fail(SGH_ERR_ARG, "sgh_plan_execute_out needs a plan created with SGH_PLAN_RELATIVE");
+    if (!src_base || !dst_base) return fail(SGH_ERR_ARG, "null base");
+    for (const auto &g : p->grids)
+        if (reinterpret_cast<uintptr_t>(src_base) % esize_of(g.dtype) != 0 ||
+            reinterpret_cast<uintptr_t>(dst_base) % esize_of(g.dtype) != 0)
+            return fail(SGH_ERR_ALIGN, "base not aligned to %zu bytes", esize_of(g.dtype));
+    hipError_t e;
+    if (src_base == dst_base) {
+        e = plan_launch_all(p, static_cast<hipStream_t>(stream), dst_base);
+    } else {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(src_base), b = reinterpret_cast<uintptr_t>(dst_base);
+        const uintptr_t x = static_cast<uintptr_t>(p->extent);
+        if (a < b + x && b < a + x) return fail(SGH_ERR_OVERLAP, "source and destination buffers overlap");
+        e = plan_launch_out(p, static_cast<hipStream_t>(stream), src_base, dst_base);
+    }
     if (e != hipSuccess) return hip_fail(e, "plan launch");
     return SGH_OK;
 }

@@ -97,6 +97,7 @@ struct MedTask {
 // next group of rows prefetched when pf is set.
 struct PoleLaunch {
     void *data;
+    void *dst = nullptr;  // destination grid (null: in place)
     int64_t npoles;
     int64_t S;
     int32_t L;
@@ -112,6 +113,7 @@ struct PoleLaunch {
 // axis) starts (p - 1) * Sw elements further.
 struct TWLaunch {
     void *data;
+    void *dst = nullptr;  // destination grid (null: in place)
     int64_t nwg;  // pencils: (N / (n * Sw)) * mid
     int64_t mid;  // Sw / Sm
     int64_t Sw;   // stride of the walked axis (elements)
@@ -121,10 +123,10 @@ struct TWLaunch {
     int32_t ept;  // tile elements per thread (threads = 1024)
     int32_t split = 2;  // 2: two-level walk; 3: three-level walk (L = TB + 2B, ept 1)
     int32_t TB = 0;
-    // Hierarchization with the three-level walk only: the axis right after the
-    // walked one (stride n * Sw, level oL, on = 2^oL - 1 points) is transformed
-    // in the same pass by its one-shot stencil, applied as the rows are read
-    // (oL = 0: off).
+    // Hierarchization out of place with the three-level walk only: the axis
+    // right after the walked one (stride n * Sw, level oL, on = 2^oL - 1
+    // points) is transformed in the same pass by its one-shot stencil, applied
+    // as the rows are read (oL = 0: off).
     int32_t oL = 0;
     int32_t on = 0;
     int32_t xcd = 0;  // 1: consecutive pencils on one XCD (workgroup order)
@@ -202,7 +204,7 @@ struct BatchTune {
     hipError_t launch_medium_##SUF(const MedTask *dev_tasks, int32_t ntasks, const void *base,        \
                                    hipStream_t s);                                                    \
     hipError_t launch_batch_##SUF(const BatchTask *dev_tasks, int32_t ntasks, const BatchTune &t,    \
-                                  const void *base, hipStream_t s);
+                                  const void *base, const void *dbase, hipStream_t s);
 SGH_DECLARE_LAUNCHERS(f64_h)
 SGH_DECLARE_LAUNCHERS(f64_d)
 SGH_DECLARE_LAUNCHERS(f64_a)
@@ -239,14 +241,15 @@ inline hipError_t launch_box(int op, int dtype, const BoxLaunch &p, const TileTu
     SGH_ROUTE(launch_box, p, t, s);
 }
 // Batch and medium task lists hold grid addresses relative to `base` (null:
-// absolute device addresses).
+// absolute device addresses); the batch launch stores relative to `dbase`
+// (equal to base: in place).
 inline hipError_t launch_medium(int op, int dtype, const MedTask *dev_tasks, int32_t ntasks, const void *base,
                                 hipStream_t s) {
     SGH_ROUTE(launch_medium, dev_tasks, ntasks, base, s);
 }
 inline hipError_t launch_batch(int op, int dtype, const BatchTask *dev_tasks, int32_t ntasks, const BatchTune &t,
-                               const void *base, hipStream_t s) {
-    SGH_ROUTE(launch_batch, dev_tasks, ntasks, t, base, s);
+                               const void *base, const void *dbase, hipStream_t s) {
+    SGH_ROUTE(launch_batch, dev_tasks, ntasks, t, base, dbase, s);
 }
 #undef SGH_ROUTE
 

@@ -64,6 +64,9 @@ def lib():
             "sgh_dehierarchize": ([G, i32, vp], ctypes.c_int),
             "sgh_hierarchize_adjoint": ([G, i32, vp], ctypes.c_int),
             "sgh_transform": ([i32, G, i32, vp], ctypes.c_int),
+            "sgh_transform_out": ([i32, G, G, i32, vp], ctypes.c_int),
+            "sgh_plan_execute_out": ([vp, vp, vp, vp], ctypes.c_int),
+            "sgh_schedule_describe_out": ([i32, G, ctypes.c_char_p, i32], ctypes.c_int),
             "sgh_plan_create": ([ctypes.POINTER(vp), i32, G, i32, u32], ctypes.c_int),
             "sgh_plan_execute": ([vp, vp], ctypes.c_int),
             "sgh_plan_execute_at": ([vp, vp, vp], ctypes.c_int),
@@ -197,6 +200,23 @@ def transform(op: int, tensors, levels, stream=None):
     return tensors
 
 
+def transform_out(op: int, src, dst, levels, stream=None):
+    """dst[i] = op(src[i]) (src unchanged); dst[i] may be src[i] itself (in place)."""
+    if not isinstance(src, (list, tuple)):
+        src, dst, levels = [src], [dst], [levels]
+    levels = _levels_list(src, levels)
+    if len(dst) != len(src):
+        raise ValueError("need one destination per source")
+    sd = [describe_tensor(t, l) for t, l in zip(src, levels)]
+    dd = [describe_tensor(t, l) for t, l in zip(dst, levels)]
+    for a, b in zip(src, dst):
+        if a.dtype != b.dtype:
+            raise ValueError("source and destination dtypes differ")
+    _check(lib().sgh_transform_out(op, grid_array(sd), grid_array(dd), len(sd), _stream_handle(stream)),
+           "sgh_transform_out")
+    return dst
+
+
 def hierarchize(tensors, levels, stream=None):
     return transform(OP_HIERARCHIZE, tensors, levels, stream)
 
@@ -286,14 +306,25 @@ class FlatPlan:
         """The grids of a flat tensor, as views of their shapes."""
         return [flat[a:a + n].view(shape_of(lv)) for a, n, lv in zip(self.starts, self.sizes, self.levels)]
 
-    def execute(self, flat, stream=None):
+    def _check_flat(self, flat):
         import torch
         want = torch.float64 if self.dtype == F64 else torch.float32
         if flat.dtype != want or not flat.is_cuda or not flat.is_contiguous() or flat.numel() != self.total:
             raise ValueError("flat buffer must be a contiguous %s device tensor of %d elements" % (want, self.total))
+
+    def execute(self, flat, stream=None):
+        self._check_flat(flat)
         _check(lib().sgh_plan_execute_at(self._h, ctypes.c_void_p(flat.data_ptr()), _stream_handle(stream)),
                "sgh_plan_execute_at")
         return flat
+
+    def execute_out(self, src, dst, stream=None):
+        """dst = op(src) for every grid of the layout (src unchanged)."""
+        self._check_flat(src)
+        self._check_flat(dst)
+        _check(lib().sgh_plan_execute_out(self._h, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                          _stream_handle(stream)), "sgh_plan_execute_out")
+        return dst
 
     def describe(self) -> dict:
         need = lib().sgh_plan_describe(self._h, None, 0)
@@ -423,14 +454,16 @@ def num_points(levels, dtype: int = F64) -> int:
     return int(lib().sgh_num_points(ctypes.byref(g)))
 
 
-def schedule(op: int, levels, dtype: int = F64) -> dict:
-    """The launch schedule the library uses for one grid (host only)."""
+def schedule(op: int, levels, dtype: int = F64, out_of_place: bool = False) -> dict:
+    """The launch schedule the library uses for one grid (host only), in place
+    or out of place (transform_out)."""
     g = make_grid(levels, dtype, 0)
-    need = lib().sgh_schedule_describe(op, ctypes.byref(g), None, 0)
+    fn = lib().sgh_schedule_describe_out if out_of_place else lib().sgh_schedule_describe
+    need = fn(op, ctypes.byref(g), None, 0)
     if need < 0:
         _check(need, "sgh_schedule_describe")
     buf = ctypes.create_string_buffer(need)
-    lib().sgh_schedule_describe(op, ctypes.byref(g), buf, len(buf))
+    fn(op, ctypes.byref(g), buf, len(buf))
     return json.loads(buf.value.decode())
 
 

@@ -93,34 +93,40 @@ def test_num_points():
 
 
 def test_schedules():
-    # hierarchization: axis 0 in an LDS tile fused with axis 1 walked in
-    # registers (each workgroup streams one contiguous plane), and axis 2's
-    # one-shot stencil applied as the plane's rows are read: one launch
+    # in place: axis 0 in an LDS tile fused with axis 1 walked in registers
+    # (each workgroup streams one contiguous plane); axis 2 strided
     s = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D)
-    assert [(l["kind"], tuple(l["axes"])) for l in s["launches"]] == [("tw", (0, 1, 2))]
-    assert (s["launches"][0]["L"], s["launches"][0]["outer_level"]) == (9, 8)
-    assert s["hbm_round_trips"] == 1
+    kinds = [(l["kind"], tuple(l["axes"])) for l in s["launches"]]
+    assert kinds == [("tw", (0, 1)), ("pole", (2,))]
+    assert [l.get("L") for l in s["launches"]] == [9, 8]
+    assert [(l["split"], l["TB"], l["B"]) for l in s["launches"]] == [(3, 3, 3), (3, 2, 3)]
+    assert s["launches"][1]["prefetch"] == 1 and s["launches"][0]["outer_level"] == 0
+    assert s["hbm_round_trips"] == 2
+    # out of place the hierarchization also folds axis 2 (its one-shot stencil
+    # applied as each plane's rows are read): one launch
+    so = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D, out_of_place=True)
+    assert [(l["kind"], tuple(l["axes"])) for l in so["launches"]] == [("tw", (0, 1, 2))]
+    assert (so["launches"][0]["L"], so["launches"][0]["outer_level"]) == (9, 8)
+    assert so["hbm_round_trips"] == 1
     try:
         sgh.set_outer_stencil(0)
-        s = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D)
-        kinds = [(l["kind"], tuple(l["axes"])) for l in s["launches"]]
-        # axis 2 in its own strided launch
-        assert kinds == [("tw", (0, 1)), ("pole", (2,))]
-        assert [l.get("L") for l in s["launches"]] == [9, 8]
-        assert [(l["split"], l["TB"], l["B"]) for l in s["launches"]] == [(3, 3, 3), (3, 2, 3)]
-        assert s["launches"][1]["prefetch"] == 1
-        assert s["hbm_round_trips"] == 2
+        so = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_3D, out_of_place=True)
+        assert [(l["kind"], tuple(l["axes"])) for l in so["launches"]] == [("tw", (0, 1)), ("pole", (2,))]
     finally:
         sgh.set_outer_stencil(1)
     with pytest.raises(sgh.SghError):
         sgh.set_outer_stencil(2)
-    # only the hierarchization has the one-shot stencil; a two-level walk folds nothing
+    # only the hierarchization has the one-shot stencil, only out of place; a
+    # two-level walk folds nothing
     for lv in ((10, 9, 8), (10, 7, 3, 2), (9, 8, 5)):
-        for op in (sgh.OP_DEHIERARCHIZE, sgh.OP_ADJOINT):
+        for op in (sgh.OP_HIERARCHIZE, sgh.OP_DEHIERARCHIZE, sgh.OP_ADJOINT):
             assert all(l.get("outer_level", 0) == 0 for l in sgh.schedule(op, lv)["launches"])
-    assert [tuple(l["axes"]) for l in sgh.schedule(sgh.OP_HIERARCHIZE, (10, 7, 3, 2))["launches"]] == [
-        (0, 1, 2), (3,)]
-    assert sgh.schedule(sgh.OP_HIERARCHIZE, (10, 4, 8))["launches"][0]["outer_level"] == 0
+            if op != sgh.OP_HIERARCHIZE:
+                assert all(l.get("outer_level", 0) == 0
+                           for l in sgh.schedule(op, lv, out_of_place=True)["launches"])
+    assert [tuple(l["axes"]) for l in sgh.schedule(sgh.OP_HIERARCHIZE, (10, 7, 3, 2), out_of_place=True)[
+        "launches"]] == [(0, 1, 2), (3,)]
+    assert sgh.schedule(sgh.OP_HIERARCHIZE, (10, 4, 8), out_of_place=True)["launches"][0]["outer_level"] == 0
     d = sgh.schedule(sgh.OP_DEHIERARCHIZE, W.ANISO_3D)
     assert [tuple(l["axes"]) for l in d["launches"]] == [(2,), (0, 1)]
     s5 = sgh.schedule(sgh.OP_HIERARCHIZE, W.ANISO_5D)
@@ -257,6 +263,24 @@ def test_batch_classes_knob():
     for bad in ((-1, 1), (4096, 0)):
         with pytest.raises(sgh.SghError):
             sgh.set_batch_classes(*bad)
+
+
+def test_transform_out_validation():
+    # rejected on the host before anything is launched (no device needed)
+    import ctypes
+    src = sgh.grid_array([fake((5, 5), ptr=0x100000)])
+    bad = [(fake((5, 5), ptr=0x100000 + 8 * 100), sgh.ERR_OVERLAP),   # overlaps the source
+           (fake((5, 4), ptr=0x200000), sgh.ERR_ARG),                   # other shape
+           (fake((5, 5), dtype=sgh.F32, ptr=0x200000), sgh.ERR_ARG),    # other dtype
+           (fake((5, 5), ptr=0x200004), sgh.ERR_ALIGN)]
+    for g, code in bad:
+        assert sgh.lib().sgh_transform_out(0, src, sgh.grid_array([g]), 1, None) == code
+    two_src = sgh.grid_array([fake((3,), ptr=0x100000), fake((3,), ptr=0x101000)])
+    # destination 0 on top of source 1
+    two_dst = sgh.grid_array([fake((3,), ptr=0x101000), fake((3,), ptr=0x300000)])
+    assert sgh.lib().sgh_transform_out(0, two_src, two_dst, 2, None) == sgh.ERR_OVERLAP
+    assert sgh.lib().sgh_transform_out(7, src, src, 1, None) == sgh.ERR_ARG
+    assert sgh.lib().sgh_transform_out(0, src, src, 0, None) == sgh.OK  # nothing to do
 
 
 def test_plain_descriptor_may_not_be_null():

@@ -194,6 +194,22 @@ def test_flat_plan_equals_plan_and_rebases():
             torch.cuda.synchronize()
             for a, b in zip(flat.views(buf), ts):
                 assert torch.equal(a, b), OP_NAME[op]
+        # out of place: the source buffer is unchanged; the small grids equal the
+        # plan bit for bit, the large ones (whose hierarchization may fold an axis
+        # into the fused launch) the oracle within tolerance
+        src = torch.empty(flat.total, dtype=torch.float64, device="cuda")
+        for v, x in zip(flat.views(src), xs):
+            v.copy_(torch.from_numpy(x))
+        keep = src.clone()
+        dst = torch.full_like(src, float("nan"))
+        flat.execute_out(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, keep)
+        for i, (a, b, x, l) in enumerate(zip(flat.views(dst), ts, xs, lv)):
+            if i < len(lv) - 2:
+                assert torch.equal(a, b), OP_NAME[op]
+            else:
+                assert rel_err(op, x, a.cpu().numpy(), ORACLE[op](x, l)) <= TOL[np.float64], (OP_NAME[op], l)
         # a relative plan refuses the plain execute
         assert sgh.lib().sgh_plan_execute(flat._h, None) == sgh.ERR_ARG
         plan.close()

@@ -261,33 +261,67 @@ def test_shape_checks_in_binding():
 FOLDED = [(10, 7, 3), (10, 8, 2), (9, 9, 4), (10, 9, 1, 3), (10, 7, 5, 2), (8, 7, 6), (3, 3, 9, 5), (7, 8, 7)]
 
 
+def gpu_run_out(op, x, levels):
+    src = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    keep = src.clone()
+    dst = torch.full_like(src, float("nan"))
+    sgh.transform_out(op, src, dst, levels)
+    torch.cuda.synchronize()
+    assert torch.equal(src, keep)  # the source is left unchanged
+    return dst.cpu().numpy()
+
+
 @pytest.mark.parametrize("levels", FOLDED, ids=ids)
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
 def test_folded_outer_axis(levels, dtype):
-    """Hierarchization with the axis after a three-level walk folded into the
-    fused launch (its one-shot stencil applied as the rows are read): against
-    the oracle, against the schedule with that axis in its own launch, and with
-    the pencils dealt to XCDs in runs (bit for bit the same arithmetic)."""
+    """Out-of-place hierarchization with the axis after a three-level walk
+    folded into the fused launch (its one-shot stencil applied as the rows are
+    read): against the oracle, against the schedule with that axis in its own
+    launch, and with the pencils dealt to XCDs in runs (the same arithmetic, bit
+    for bit)."""
     code = sgh.F64 if dtype == np.float64 else sgh.F32
-    sched = sgh.schedule(sgh.OP_HIERARCHIZE, levels, code)
+    sched = sgh.schedule(sgh.OP_HIERARCHIZE, levels, code, out_of_place=True)
     tw = sched["launches"][0]
     assert tw["kind"] == "tw" and tw["split"] == 3 and tw["outer_level"] > 0, sched
     x = W.uniform(levels, [29, len(levels)], dtype)
     x64 = x.astype(np.float64)
     ref = oracle.hierarchize(x64, levels)
-    got = gpu_run(sgh.OP_HIERARCHIZE, x, levels)
+    got = gpu_run_out(sgh.OP_HIERARCHIZE, x, levels)
     err = rel_err(sgh.OP_HIERARCHIZE, x64, got, ref)
     print("folded levels=%s %s: err %.3e" % (levels, np.dtype(dtype).name, err), flush=True)
     assert err <= TOL[dtype]
     try:
         sgh.set_xcd_order(1)
-        assert sgh.schedule(sgh.OP_HIERARCHIZE, levels, code)["launches"][0]["xcd_order"] == 1
-        np.testing.assert_array_equal(gpu_run(sgh.OP_HIERARCHIZE, x, levels), got)
+        assert sgh.schedule(sgh.OP_HIERARCHIZE, levels, code, out_of_place=True)["launches"][0]["xcd_order"] == 1
+        np.testing.assert_array_equal(gpu_run_out(sgh.OP_HIERARCHIZE, x, levels), got)
         sgh.set_xcd_order(0)
         sgh.set_outer_stencil(0)
-        assert sgh.schedule(sgh.OP_HIERARCHIZE, levels, code)["launches"][0]["outer_level"] == 0
-        unfolded = gpu_run(sgh.OP_HIERARCHIZE, x, levels)
+        assert sgh.schedule(sgh.OP_HIERARCHIZE, levels, code, out_of_place=True)["launches"][0]["outer_level"] == 0
+        unfolded = gpu_run_out(sgh.OP_HIERARCHIZE, x, levels)
         assert float(np.max(np.abs(unfolded.astype(np.float64) - got))) <= 2 * TOL[dtype] * np.abs(x64).max()
     finally:
         sgh.set_xcd_order(0)
         sgh.set_outer_stencil(1)
+
+
+OUT_SHAPES = [(5, 5), (10, 9, 3), (6, 6, 5, 5), (14,), (5, 12), (6,) + (2,) * 9, (10, 4, 3), (3, 2, 4)]
+
+
+@pytest.mark.parametrize("levels", OUT_SHAPES, ids=ids)
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_transform_out_all_ops(levels, dtype):
+    """Out of place, every operation and schedule kind (tile, fused, pole,
+    split, box): the destination equals the oracle and the source is unchanged;
+    dst == src is the in-place transform."""
+    x = W.uniform(levels, [31, len(levels)], dtype)
+    x64 = x.astype(np.float64)
+    for op in OPS:
+        ref = ORACLE[op](x64, levels)
+        got = gpu_run_out(op, x, levels)
+        err = rel_err(op, x64, got, ref)
+        print("out levels=%s %s %s: err %.3e" % (levels, np.dtype(dtype).name, OP_NAME[op], err), flush=True)
+        assert err <= TOL[dtype], (OP_NAME[op], err)
+        t = torch.from_numpy(x.copy()).cuda()
+        sgh.transform_out(op, t, t, levels)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(t.cpu().numpy(), gpu_run(op, x, levels))
