@@ -172,6 +172,21 @@ int sgh_plan_set_data(sgh_plan *plan, const sgh_grid *grids, int32_t n);
 int sgh_plan_describe(const sgh_plan *plan, char *buf, int32_t len);
 void sgh_plan_destroy(sgh_plan *plan);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops): op applied in place to every grid in one call, with
+ * no plan and no allocation.  The grids that fit the on-chip tile (at most
+ * SGH_STATIC_TASKS of them, else SGH_ERR_UNSUPPORTED before anything is
+ * launched) go to the batch launch, whose task list is copied into a
+ * fixed-size device array that the library holds on every device it has
+ * run on (about 1.4 MB, until the process ends); larger grids get their own
+ * launches, which use no device memory beyond the grid.  The array is
+ * shared by every call on a device and keeps the last call's contents:
+ * calls on one stream are ordered, but calls on one device from different
+ * streams or threads that overlap in time race for it.  Same results, bit
+ * for bit, as a plan without autotuning (sgh_plan_create + execute). */
+#define SGH_STATIC_TASKS 4096
+int sgh_transform_batch_static(int32_t op, const sgh_grid *grids, int32_t n, void *stream);
+
 /* ---- combination technique: sparse grid of a combination set ------------
  *
  * Hierarchization is what makes the combination technique's communication

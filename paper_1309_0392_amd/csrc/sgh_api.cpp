@@ -1497,8 +1497,121 @@ int max_lds_bytes() { return dev_info().max_lds_block; }
 }  // namespace sgh
 
 // ---------------------------------------------------------------------------
+// Batched transform that allocates nothing: the task list of the batch launch
+// lives in a file-scope device array (each device holds its own copy until the
+// process ends).  Host code never passes the array's name to a kernel; it
+// passes the device address hipGetSymbolAddress returns for the current
+// device, looked up once per device.
+namespace sgh {
+constexpr int kStaticTasks = SGH_STATIC_TASKS;  // grids per call that the batch launch takes
+constexpr int kMaxDevices = 64;
+}  // namespace sgh
+
+static __device__ __align__(256) sgh::BatchTask scratch[sgh::kStaticTasks];
+
+namespace sgh {
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+int scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(SGH_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress");
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return SGH_OK;
+}
+
+int transform_batch_static(int op, const sgh_grid *grids, int32_t n, void *stream) {
+    if (op < 0 || op > 2) return fail(SGH_ERR_ARG, "unknown op %d", op);
+    int rc = validate_all(grids, n);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // grids that fit one workgroup's LDS go to the batch launch (largest
+    // first, one group per dtype); the others get their own launches
+    std::vector<std::pair<int64_t, int>> small[2];
+    std::vector<int> large;
+    for (int i = 0; i < n; ++i) {
+        const Geom g = make_geom(grids[i]);
+        if (g.d == 0) continue;
+        if (g.N * static_cast<int64_t>(esize_of(g.dtype)) <= batch_lds_limit(g.dtype))
+            small[g.dtype].push_back({g.N, i});
+        else
+            large.push_back(i);
+    }
+    const size_t ntasks = small[0].size() + small[1].size();
+    if (ntasks > static_cast<size_t>(kStaticTasks))
+        return fail(SGH_ERR_UNSUPPORTED, "%zu grids fit the batch tile; this entry point takes at most %d", ntasks,
+                    kStaticTasks);
+    std::vector<std::vector<Step>> steps(large.size());
+    for (size_t j = 0; j < large.size(); ++j) {
+        steps[j] = build_schedule(op, make_geom(grids[large[j]]));
+        for (auto &s : steps[j])
+            if (!step_launchable(s))
+                return fail(SGH_ERR_UNSUPPORTED, "grid %d: no %s kernel for this shape under the current tuning knobs",
+                            large[j], step_name(s));
+    }
+    void *dev = nullptr;
+    rc = scratch_address(&dev);
+    if (rc) return rc;
+    if (ntasks) {
+        thread_local std::vector<BatchTask> host;
+        host.clear();
+        for (int dt = 0; dt < 2; ++dt) {
+            auto &v = small[dt];
+            std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+            for (auto &x : v) {
+                const Geom g = make_geom(grids[x.second]);
+                BatchTask t{};
+                t.data = g.data;
+                t.N = static_cast<int32_t>(g.N);
+                t.g = make_tile_geom(g, g.d);
+                host.push_back(t);
+            }
+        }
+        hipError_t e = hipMemcpyAsync(dev, host.data(), host.size() * sizeof(BatchTask), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "task upload");
+        const DevInfo &di = dev_info();
+        size_t first = 0;
+        for (int dt = 0; dt < 2; ++dt) {
+            if (small[dt].empty()) continue;
+            BatchTune tune;
+            batch_default_tune(di, static_cast<int>(small[dt].front().first), static_cast<int>(small[dt].size()), dt,
+                               &tune);
+            e = launch_batch(op, dt, static_cast<BatchTask *>(dev) + first, static_cast<int32_t>(small[dt].size()),
+                             tune, nullptr, nullptr, st);
+            if (e != hipSuccess) return hip_fail(e, "batch launch");
+            first += small[dt].size();
+        }
+    }
+    for (size_t j = 0; j < large.size(); ++j)
+        for (auto &s : steps[j]) {
+            hipError_t e = run_step(op, grids[large[j]].dtype, s, st);
+            if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        }
+    return SGH_OK;
+}
+
+}  // namespace
+}  // namespace sgh
+
+// ---------------------------------------------------------------------------
 // C ABI
 extern "C" {
+
+int sgh_transform_batch_static(int32_t op, const sgh_grid *grids, int32_t n, void *stream) {
+    return sgh::transform_batch_static(op, grids, n, stream);
+}
 
 int sgh_hierarchize(const sgh_grid *grids, int32_t n, void *stream) {
     return sgh::transform(SGH_OP_HIERARCHIZE, grids, n, stream);

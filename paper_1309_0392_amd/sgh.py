@@ -18,6 +18,7 @@ import os
 from typing import List, Optional, Sequence
 
 MAX_DIM = 16
+STATIC_TASKS = 4096  # grids per sgh_transform_batch_static call that fit the batch tile
 MAX_LEVEL = 30
 F32, F64 = 0, 1
 OP_HIERARCHIZE, OP_DEHIERARCHIZE, OP_ADJOINT = 0, 1, 2
@@ -65,6 +66,7 @@ def lib():
             "sgh_hierarchize_adjoint": ([G, i32, vp], ctypes.c_int),
             "sgh_transform": ([i32, G, i32, vp], ctypes.c_int),
             "sgh_transform_out": ([i32, G, G, i32, vp], ctypes.c_int),
+            "sgh_transform_batch_static": ([i32, G, i32, vp], ctypes.c_int),
             "sgh_plan_execute_out": ([vp, vp, vp, vp], ctypes.c_int),
             "sgh_schedule_describe_out": ([i32, G, ctypes.c_char_p, i32], ctypes.c_int),
             "sgh_plan_create": ([ctypes.POINTER(vp), i32, G, i32, u32], ctypes.c_int),

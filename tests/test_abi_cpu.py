@@ -37,6 +37,7 @@ def test_header_constants_match_binding():
     assert int(consts["SGH_ERR_OVERLAP"]) == sgh.ERR_OVERLAP
     assert int(consts["SGH_PLAN_GRAPH"].rstrip("u")) == sgh.PLAN_GRAPH
     assert int(consts["SGH_PLAN_RELATIVE"].rstrip("u")) == sgh.PLAN_RELATIVE
+    assert int(consts["SGH_STATIC_TASKS"]) == sgh.STATIC_TASKS
     # struct layout: dim, level[16], dtype, data pointer
     assert ctypes.sizeof(sgh.SghGrid) == 80 and sgh.SghGrid.data.offset == 72
 
@@ -281,6 +282,16 @@ def test_transform_out_validation():
     assert sgh.lib().sgh_transform_out(0, two_src, two_dst, 2, None) == sgh.ERR_OVERLAP
     assert sgh.lib().sgh_transform_out(7, src, src, 1, None) == sgh.ERR_ARG
     assert sgh.lib().sgh_transform_out(0, src, src, 0, None) == sgh.OK  # nothing to do
+
+
+def test_static_batch_rejects_too_many_grids_before_launch():
+    # more small grids than the fixed device task array holds: refused on the
+    # host before any device call (no device needed)
+    n = sgh.STATIC_TASKS + 1
+    grids = sgh.grid_array([fake((2,), ptr=0x100000 + 64 * i) for i in range(n)])
+    assert sgh.lib().sgh_transform_batch_static(0, grids, n, None) == sgh.ERR_UNSUPPORTED
+    assert "at most %d" % sgh.STATIC_TASKS in sgh.last_error_message()
+    assert sgh.lib().sgh_transform_batch_static(5, grids, 1, None) == sgh.ERR_ARG
 
 
 def test_plain_descriptor_may_not_be_null():
