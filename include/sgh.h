@@ -309,9 +309,12 @@ int sgh_set_medium_limits(int64_t max_points, int32_t min_grids);
 /* Tuning knob for plans: the small grids of one dtype are split into size
  * classes (one batch launch per class of up to 8, 16, 32, 64 KiB per grid)
  * when there are at least `min_grids` of them (0: never split); a class of
- * fewer than `min_per_class` (>= 1) grids joins the next larger class.
- * Defaults 4096 and 1024.  Applies to plans built after the call. */
-int sgh_set_batch_classes(int32_t min_grids, int32_t min_per_class);
+ * fewer than `min_per_class` (>= 1) grids joins the next larger class.  With
+ * `concurrent` = 1 the class launches after the first go out on streams of
+ * the plan's own, forked from the caller's stream and joined back to it (so
+ * that they overlap); 0 issues them one after another on the caller's
+ * stream.  Defaults 4096, 1024, 1.  Applies to plans built after the call. */
+int sgh_set_batch_classes(int32_t min_grids, int32_t min_per_class, int32_t concurrent);
 
 /* Schedule switch: level 1 (default) fuses the leading LDS-tile axes with one
  * strided axis walked in registers into a single launch (one HBM round trip

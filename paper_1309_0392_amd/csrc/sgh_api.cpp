@@ -982,6 +982,7 @@ int g_medium_min = 16;
 // launch (each class launch would be too short to fill the GPU).
 int g_class_min_grids = 4096;
 int g_class_min_per = 1024;
+int g_class_streams = 1;  // class launches after the first on forked streams
 
 // Can one workgroup take grid g in passes through its tile?  Fills the task:
 // after the tile pass, runs of consecutive axes share one box pass while the
@@ -1080,6 +1081,11 @@ struct sgh_plan {
     int op = 0;
     uint32_t flags = 0;
     bool relative = false;  // grid data fields are byte offsets into the buffer given at execute
+    // size classes after the first run on their own streams, forked from and
+    // joined back to the caller's stream (their launches overlap)
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
     int64_t extent = 0;     // relative plans: bytes from offset 0 to the end of the last grid
     std::vector<sgh_grid> grids;
     std::vector<sgh::BatchGroup> groups;
@@ -1117,6 +1123,37 @@ void fill_med_tasks(const sgh_plan &p, const MedGroup &mg, std::vector<MedTask> 
 
 std::string op_prefix(int op) { return op == 0 ? "hier" : op == 1 ? "dehier" : "adjoint"; }
 
+// The batch launches of a plan (one per size class); classes after the first
+// on the plan's side streams, forked from and joined back to `st`.
+hipError_t plan_launch_batches(sgh_plan *p, hipStream_t st, const void *base, const void *dbase) {
+    const size_t ng = p->groups.size();
+    const bool forked = ng > 1 && p->side.size() + 1 >= ng;
+    if (forked) {
+        hipError_t e = hipEventRecord(p->fork, st);
+        if (e != hipSuccess) return e;
+    }
+    for (size_t i = 0; i < ng; ++i) {
+        auto &bg = p->groups[i];
+        hipStream_t s = (forked && i > 0) ? p->side[i - 1] : st;
+        if (forked && i > 0) {
+            hipError_t e = hipStreamWaitEvent(s, p->fork, 0);
+            if (e != hipSuccess) return e;
+        }
+        {
+            TimerScope ts(op_prefix(p->op) + (bg.dtype == SGH_F64 ? "_f64" : "_f32") + "_batch" + bg.suffix, s);
+            hipError_t e = launch_batch(p->op, bg.dtype, bg.dev_tasks, static_cast<int32_t>(bg.grid_idx.size()),
+                                        bg.tune, base, dbase, s);
+            if (e != hipSuccess) return e;
+        }
+        if (forked && i > 0) {
+            hipError_t e = hipEventRecord(p->joins[i - 1], s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, p->joins[i - 1], 0);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
 // A relative plan out of place: the grids at src + offset are transformed into
 // dst + offset.  The batch launches read src and write dst; with medium grids
 // the whole extent is copied first and those run in place on dst; large grids
@@ -1126,10 +1163,8 @@ hipError_t plan_launch_out(sgh_plan *p, hipStream_t st, const void *src, void *d
         hipError_t e = hipMemcpyAsync(dst, src, static_cast<size_t>(p->extent), hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
     }
-    for (auto &bg : p->groups) {
-        TimerScope ts(op_prefix(p->op) + (bg.dtype == SGH_F64 ? "_f64" : "_f32") + "_batch" + bg.suffix, st);
-        hipError_t e = launch_batch(p->op, bg.dtype, bg.dev_tasks, static_cast<int32_t>(bg.grid_idx.size()), bg.tune,
-                                    src, dst, st);
+    {
+        hipError_t e = plan_launch_batches(p, st, src, dst);
         if (e != hipSuccess) return e;
     }
     for (auto &mg : p->medium) {
@@ -1162,12 +1197,8 @@ hipError_t plan_launch_out(sgh_plan *p, hipStream_t st, const void *src, void *d
 // Every launch of a plan on `st`; base is null, or the buffer a relative
 // plan's offsets point into.
 hipError_t plan_launch_all(sgh_plan *p, hipStream_t st, const void *base = nullptr) {
-    for (auto &bg : p->groups) {
-        TimerScope ts(op_prefix(p->op) + (bg.dtype == SGH_F64 ? "_f64" : "_f32") + "_batch" + bg.suffix, st);
-        hipError_t e = launch_batch(p->op, bg.dtype, bg.dev_tasks, static_cast<int32_t>(bg.grid_idx.size()), bg.tune,
-                                    base, base, st);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e0 = plan_launch_batches(p, st, base, base);
+    if (e0 != hipSuccess) return e0;
     for (auto &mg : p->medium) {
         TimerScope ts(op_prefix(p->op) + (mg.dtype == SGH_F64 ? "_f64" : "_f32") + "_medium", st);
         hipError_t e =
@@ -1461,6 +1492,9 @@ void plan_free(sgh_plan *p) {
     for (auto &bg : p->groups) {
         if (bg.dev_tasks) (void)hipFree(bg.dev_tasks);
     }
+    for (auto s : p->side) (void)hipStreamDestroy(s);
+    for (auto e : p->joins) (void)hipEventDestroy(e);
+    if (p->fork) (void)hipEventDestroy(p->fork);
     for (auto &mg : p->medium) {
         if (mg.dev_tasks) (void)hipFree(mg.dev_tasks);
     }
@@ -1788,6 +1822,18 @@ int sgh_plan_create(sgh_plan **plan, int32_t op, const sgh_grid *grids, int32_t 
             p->groups.push_back(bg);
         }
     }
+    if (p->groups.size() > 1 && g_class_streams) {
+        hipError_t e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+        for (size_t i = 1; e == hipSuccess && i < p->groups.size(); ++i) {
+            hipStream_t s = nullptr;
+            hipEvent_t j = nullptr;
+            e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+            if (e == hipSuccess) p->side.push_back(s);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+            if (e == hipSuccess) p->joins.push_back(j);
+        }
+        if (e != hipSuccess) return hip_fail(e, "class streams");
+    }
     if (flags & SGH_PLAN_AUTOTUNE) {
         for (auto &bg : p->groups) {
             rc = autotune_group(p.get(), bg);
@@ -1996,13 +2042,15 @@ int sgh_set_medium_limits(int64_t max_points, int32_t min_grids) {
     return SGH_OK;
 }
 
-int sgh_set_batch_classes(int32_t min_grids, int32_t min_per_class) {
+int sgh_set_batch_classes(int32_t min_grids, int32_t min_per_class, int32_t concurrent) {
     using namespace sgh;
-    if (min_grids < 0 || min_per_class < 1)
-        return fail(SGH_ERR_ARG, "batch class limits %d, %d outside >= 0, >= 1", min_grids, min_per_class);
+    if (min_grids < 0 || min_per_class < 1 || concurrent < 0 || concurrent > 1)
+        return fail(SGH_ERR_ARG, "batch class limits %d, %d, %d outside >= 0, >= 1, 0..1", min_grids, min_per_class,
+                    concurrent);
     std::lock_guard<std::mutex> lk(g_override_mu);
     g_class_min_grids = min_grids;
     g_class_min_per = min_per_class;
+    g_class_streams = concurrent;
     return SGH_OK;
 }
 

@@ -72,7 +72,7 @@ def lib():
             "sgh_plan_create": ([ctypes.POINTER(vp), i32, G, i32, u32], ctypes.c_int),
             "sgh_plan_execute": ([vp, vp], ctypes.c_int),
             "sgh_plan_execute_at": ([vp, vp, vp], ctypes.c_int),
-            "sgh_set_batch_classes": ([i32, i32], ctypes.c_int),
+            "sgh_set_batch_classes": ([i32, i32, i32], ctypes.c_int),
             "sgh_set_outer_stencil": ([i32], ctypes.c_int),
             "sgh_set_xcd_order": ([i32], ctypes.c_int),
             "sgh_plan_set_data": ([vp, G, i32], ctypes.c_int),
@@ -490,10 +490,12 @@ def set_box_limits(max_bytes: int = 0, min_row_bytes: int = 0):
     _check(lib().sgh_set_box_limits(int(max_bytes), int(min_row_bytes)), "sgh_set_box_limits")
 
 
-def set_batch_classes(min_grids: int = 4096, min_per_class: int = 1024):
+def set_batch_classes(min_grids: int = 4096, min_per_class: int = 1024, concurrent: int = 1):
     """Plans: split the small grids of one dtype into size classes (one batch launch each) when there
-    are at least min_grids of them (0 = never); classes below min_per_class grids join the next one."""
-    _check(lib().sgh_set_batch_classes(int(min_grids), int(min_per_class)), "sgh_set_batch_classes")
+    are at least min_grids of them (0 = never); classes below min_per_class grids join the next one;
+    concurrent=1 overlaps the class launches on forked streams."""
+    _check(lib().sgh_set_batch_classes(int(min_grids), int(min_per_class), int(concurrent)),
+           "sgh_set_batch_classes")
 
 
 def set_outer_stencil(on: int = 1):

@@ -261,7 +261,7 @@ def test_batch_classes_knob():
     sgh.set_batch_classes(0, 1)
     sgh.set_batch_classes(10, 5)
     sgh.set_batch_classes()
-    for bad in ((-1, 1), (4096, 0)):
+    for bad in ((-1, 1), (4096, 0), (4096, 1, 2)):
         with pytest.raises(sgh.SghError):
             sgh.set_batch_classes(*bad)
 

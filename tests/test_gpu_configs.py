@@ -247,3 +247,39 @@ def test_size_classes_bitwise_equal_to_one_launch(dtype):
             p2.close()
     finally:
         sgh.set_batch_classes()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_size_classes_concurrent_graph_replays(dtype):
+    """Size classes on forked streams, with a grid beyond the tile, captured in
+    one graph: every replay (eager work on the stream between replays) equals
+    the classes issued one after another on one stream, bit for bit."""
+    lv, _, xs = combi(dtype)
+    lv = lv + [(10, 9, 3)]
+    xs = xs + [W.uniform((10, 9, 3), 61, dtype)]
+    ta = [torch.from_numpy(x.copy()).cuda() for x in xs]
+    tb = [torch.from_numpy(x.copy()).cuda() for x in xs]
+    scratch = torch.randn(1 << 20, device="cuda")
+    try:
+        for op in ORACLE:
+            sgh.set_batch_classes(1, 1, 0)
+            serial = sgh.Plan(op, tb, lv, graph=False)
+            sgh.set_batch_classes(1, 1, 1)
+            forked = sgh.Plan(op, ta, lv, graph=True)
+            d = forked.describe()
+            assert len(d["batches"]) > 1 and d["graph"] is True
+            for t, x in zip(tb, xs):
+                t.copy_(torch.from_numpy(x))
+            serial.execute()
+            for rep in range(3):
+                for t, x in zip(ta, xs):
+                    t.copy_(torch.from_numpy(x))
+                forked.execute()
+                scratch.mul_(1.0001)
+                torch.cuda.synchronize()
+                for i, (a, b) in enumerate(zip(ta, tb)):
+                    assert torch.equal(a, b), (OP_NAME[op], rep, lv[i])
+            serial.close()
+            forked.close()
+    finally:
+        sgh.set_batch_classes()
