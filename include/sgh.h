@@ -313,7 +313,7 @@ int sgh_set_medium_limits(int64_t max_points, int32_t min_grids);
  * `concurrent` = 1 the class launches after the first go out on streams of
  * the plan's own, forked from the caller's stream and joined back to it (so
  * that they overlap); 0 issues them one after another on the caller's
- * stream.  Defaults 4096, 1024, 1.  Applies to plans built after the call. */
+ * stream.  Defaults 4096, 1024, 0.  Applies to plans built after the call. */
 int sgh_set_batch_classes(int32_t min_grids, int32_t min_per_class, int32_t concurrent);
 
 /* Schedule switch: level 1 (default) fuses the leading LDS-tile axes with one

@@ -982,7 +982,7 @@ int g_medium_min = 16;
 // launch (each class launch would be too short to fill the GPU).
 int g_class_min_grids = 4096;
 int g_class_min_per = 1024;
-int g_class_streams = 1;  // class launches after the first on forked streams
+int g_class_streams = 0;  // 1: class launches after the first on forked streams (measured no faster)
 
 // Can one workgroup take grid g in passes through its tile?  Fills the task:
 // after the tile pass, runs of consecutive axes share one box pass while the

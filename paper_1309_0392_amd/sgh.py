@@ -490,7 +490,7 @@ def set_box_limits(max_bytes: int = 0, min_row_bytes: int = 0):
     _check(lib().sgh_set_box_limits(int(max_bytes), int(min_row_bytes)), "sgh_set_box_limits")
 
 
-def set_batch_classes(min_grids: int = 4096, min_per_class: int = 1024, concurrent: int = 1):
+def set_batch_classes(min_grids: int = 4096, min_per_class: int = 1024, concurrent: int = 0):
     """Plans: split the small grids of one dtype into size classes (one batch launch each) when there
     are at least min_grids of them (0 = never); classes below min_per_class grids join the next one;
     concurrent=1 overlaps the class launches on forked streams."""
