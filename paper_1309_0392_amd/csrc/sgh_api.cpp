@@ -1057,6 +1057,7 @@ void batch_default_tune(const DevInfo &di, int maxN, int ntasks, int dtype, Batc
     }
     t->nt = nt;
     t->ept = ept;
+    t->cus = di.cus;
     t->lds_bytes = std::max<int>(static_cast<int>(maxN * esize_of(dtype)), 16);
     // resident workgroups per CU, bounded by LDS and by waves
     const int by_lds = std::max(1, di.lds_per_cu / t->lds_bytes);
@@ -1249,9 +1250,11 @@ int plan_capture(sgh_plan *p) {
     return SGH_OK;
 }
 
-// Median time (ms) of `reps` runs of fn on a private stream.
+// Time (ms) of one run of fn on a private stream: the fastest of `reps`
+// samples, each the mean of a few back-to-back runs between two events (a
+// launch of a few microseconds is otherwise lost in the events' own cost).
 template <typename F>
-float time_median(F &&fn, hipStream_t st, int reps) {
+float time_best(F &&fn, hipStream_t st, int reps) {
     std::vector<float> t;
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return 1e30f;
@@ -1259,22 +1262,35 @@ float time_median(F &&fn, hipStream_t st, int reps) {
         (void)hipEventDestroy(a);
         return 1e30f;
     }
-    for (int r = 0; r < reps + 1; ++r) {
+    // warm up, and size the samples: short launches are repeated
+    int per = 1;
+    {
         (void)hipEventRecord(a, st);
-        if (fn(st) != hipSuccess) {
-            t.assign(1, 1e30f);
-            break;
-        }
+        hipError_t e = fn(st);
         (void)hipEventRecord(b, st);
         (void)hipEventSynchronize(b);
         float ms = 0;
         (void)hipEventElapsedTime(&ms, a, b);
-        if (r > 0) t.push_back(ms);  // first run warms up
+        if (e != hipSuccess) reps = 0, t.assign(1, 1e30f);
+        else if (ms < 0.2f) per = 8;
+    }
+    for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(a, st);
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < per && e == hipSuccess; ++i) e = fn(st);
+        (void)hipEventRecord(b, st);
+        (void)hipEventSynchronize(b);
+        if (e != hipSuccess) {
+            t.assign(1, 1e30f);
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        t.push_back(ms / static_cast<float>(per));
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    std::sort(t.begin(), t.end());
-    return t.empty() ? 1e30f : t[t.size() / 2];
+    return t.empty() ? 1e30f : *std::min_element(t.begin(), t.end());
 }
 
 // Autotune a batch group: candidate workgroup sizes, timed on a scratch copy
@@ -1327,12 +1343,12 @@ int autotune_group(sgh_plan *p, BatchGroup &bg) {
                 batch_default_tune(di, maxN, static_cast<int>(tasks.size()), bg.dtype, &t, nt, persist);
                 if (t.nt != nt || (nt == 1024 && t.ept > 8)) continue;
                 if (persist && t.nwg == static_cast<int>(tasks.size())) continue;  // same launch as persist = 0
-                const float ms = time_median(
+                const float ms = time_best(
                     [&](hipStream_t s) {
                         return launch_batch(p->op, bg.dtype, dtasks, static_cast<int32_t>(tasks.size()), t,
                                             nullptr, nullptr, s);
                     },
-                    st, 5);
+                    st, 7);
                 if (ms < best) {
                     best = ms;
                     best_nt = nt;
@@ -1410,7 +1426,7 @@ int autotune_large(sgh_plan *p, PlanLarge &lg) {
                         c.tile.chunk = static_cast<int32_t>(Sm * mult);
                         choose_tile_tune(c.tile.chunk, &c.ttune);
                         const float ms =
-                            time_median([&](hipStream_t x) { return run_step(p->op, sg.dtype, c, x); }, st, 3);
+                            time_best([&](hipStream_t x) { return run_step(p->op, sg.dtype, c, x); }, st, 3);
                         if (verbose)
                             std::fprintf(stderr, "[sgh autotune] %s tile m=%d chunk=%d: %.4f ms\n", key.c_str(),
                                          s.tile.g.m, c.tile.chunk, ms);
@@ -1423,7 +1439,7 @@ int autotune_large(sgh_plan *p, PlanLarge &lg) {
                     float best = 1e30f;
                     auto trial = [&](Step c, int code, const char *what) {
                         const float ms =
-                            time_median([&](hipStream_t x) { return run_step(p->op, sg.dtype, c, x); }, st, 3);
+                            time_best([&](hipStream_t x) { return run_step(p->op, sg.dtype, c, x); }, st, 3);
                         if (verbose)
                             std::fprintf(stderr, "[sgh autotune] %s axis %d pole L=%d %s B=%d TB=%d pf=%d nt=%d: %.4f ms\n",
                                          key.c_str(), s.key, s.pole.L, what, c.pole.B, c.pole.TB, c.pole.pf,
@@ -1461,7 +1477,7 @@ int autotune_large(sgh_plan *p, PlanLarge &lg) {
                 }
             }
             auto steps = build_schedule_opts(p->op, sg, o);
-            const float total = time_median(
+            const float total = time_best(
                 [&](hipStream_t x) {
                     for (auto &s : steps) {
                         hipError_t r = run_step(p->op, sg.dtype, s, x);

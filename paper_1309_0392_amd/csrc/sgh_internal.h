@@ -190,7 +190,8 @@ struct BatchTune {
     int ept = 8;
     int nwg = 0;        // one workgroup per grid, or the resident count (each then owns several grids)
     int lds_bytes = 0;
-    int persist = 0;    // 1: nwg = resident workgroups
+    int persist = 0;    // 1: nwg = resident workgroups (capped at launch by the kernel's occupancy)
+    int cus = 256;      // compute units of the device
 };
 
 // Launchers per element type and operation (return the first HIP error,
