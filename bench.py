@@ -163,16 +163,22 @@ def protocol(torch, fwd, inv, reps=20, cold=5):
     return out
 
 
-def timed_kernels(torch, sgh, fn, steps):
-    """ms per call of fn over `steps` calls, and the library's per-kernel report."""
+def timed_kernels(torch, sgh, fn, steps, separate=False):
+    """ms per call of fn over `steps` calls, and the library's per-kernel report
+    (HIP events around every launch, on its stream, over the same timed calls).
+    separate=True (workloads of a few microseconds, where the events' own cost
+    would show in the step time): the steps are timed without the per-launch
+    events, and the report comes from as many calls right after."""
     fn()
     torch.cuda.synchronize()
+    if separate:
+        ms = time_region(torch, fn, steps) / steps
     sgh.timing_reset()
     sgh.timing_enable(True)
-    ms = time_region(torch, fn, steps) / steps
+    ms_inst = time_region(torch, fn, steps) / steps
     report = sgh.timing_report()
     sgh.timing_enable(False)
-    return ms, report
+    return (ms if separate else ms_inst), report
 
 
 def roofline_of(report, bytes_per_launch, workload, dominant=None):
@@ -510,7 +516,7 @@ def secondary_batch(args, torch, np, sgh, W, name):
         pts["hier_%s_medium" % dt] = m["points"]
     for _ in range(args.warmup):
         plan.execute()
-    ms, rep = timed_kernels(torch, sgh, plan.execute, args.steps)
+    ms, rep = timed_kernels(torch, sgh, plan.execute, args.steps, separate=(R == 1))
     algo = lambda k: 2.0 * pts.get(k, npts) * esize
     out = {"metric": "grid points hierarchized/s (batched combination set)", "unit": "points/s",
            "value": npts / (ms * 1e-3), "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -564,7 +570,7 @@ def secondary_grad(args, torch, np, sgh, W, name):
         return g
     for _ in range(args.warmup):
         step()
-    ms, rep = timed_kernels(torch, sgh, step, args.steps)
+    ms, rep = timed_kernels(torch, sgh, step, args.steps, separate=(R == 1))
     pts = {}
     for op, plan in (("hier", fs.fwd), ("adjoint", fs.adj)):
         for b in plan.describe()["batches"]:
