@@ -64,6 +64,10 @@ def parse():
                     help="autotune the schedule of the grid first (timed trial launches on scratch grids)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only copy a buffer of the workload's size (reference kernel for HBM counters)")
+    ap.add_argument("--out-of-place", action="store_true",
+                    help="single grids: the timed step transforms into a second resident buffer (sgh_transform_out)")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the warm-up and the timed steps (no protocol, extras or CPU baseline): for profilers")
     ap.add_argument("--workload", choices=sorted(GRIDS) + sorted(SECONDARY), default="aniso3d")
     return ap.parse_args()
 
@@ -279,7 +283,11 @@ def run_grid(args, torch, np, sgh, W, name):
             tuned[op] = plan.describe()["large"][0]["launches"]
             plan.close()
 
-    step = lambda: sgh.hierarchize(x, levels)
+    if args.out_of_place:
+        y_out = torch.empty_like(x)
+        step = lambda: sgh.transform_out(sgh.OP_HIERARCHIZE, x, y_out, levels)
+    else:
+        step = lambda: sgh.hierarchize(x, levels)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -290,8 +298,10 @@ def run_grid(args, torch, np, sgh, W, name):
     report = sgh.timing_report()
     sgh.timing_enable(False)
     ms = ms_total / args.steps
-    sched = tuned.get(sgh.OP_HIERARCHIZE) or sgh.schedule(sgh.OP_HIERARCHIZE, levels, code)["launches"]
+    sched = tuned.get(sgh.OP_HIERARCHIZE) or sgh.schedule(sgh.OP_HIERARCHIZE, levels, code,
+                                                           out_of_place=args.out_of_place)["launches"]
     whole = algo / (ms * 1e-3) / 1e9
+    wl = (name if dt == "f64" else name + "_f32") + ("_out" if args.out_of_place else "")
     out = {
         "metric": METRIC if name == "aniso3d" else "grid points hierarchized/s (%s)" % name,
         "value": N / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -303,8 +313,12 @@ def run_grid(args, torch, np, sgh, W, name):
         "launches_per_step": sum(v["count"] for v in report.values()) / args.steps,
         "schedule": sched,
         "kernels": kernel_table(report, lambda k: algo),
-        "roofline": roofline_of(report, lambda k: algo, name if dt == "f64" else name + "_f32"),
+        "roofline": roofline_of(report, lambda k: algo, wl),
     }
+    if args.out_of_place:
+        out["config"]["workload"] += ", out of place into a second resident buffer"
+    if args.profile_run:
+        return out
     out["timing_protocol"] = protocol(torch, step, lambda: sgh.dehierarchize(x, levels))
     out["timing_protocol"]["points_per_s_median"] = N / (out["timing_protocol"]["forward"]["median_ms"] * 1e-3)
     out["out_of_place"] = out_of_place(args, torch, sgh, x, levels, code, algo, name if dt == "f64" else name + "_f32")
@@ -462,7 +476,7 @@ def secondary_combination(args, torch, np, sgh, W, name):
            "extras": {"scatter": {"points_per_s": npts / (ms_s * 1e-3), "ms": ms_s,
                                   "roofline": roofline_of(rep_s, lambda k: algo, name)}}}
     comb.close()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.profile_run:
         import oracle
         lv10, c10 = W.combination_set()
         hs = W.combination_values(lv10, seed=3)
@@ -532,6 +546,8 @@ def secondary_batch(args, torch, np, sgh, W, name):
     dom = "hier_%s_medium" % dt if name == "batch_d4n13" else None
     out["roofline"] = roofline_of(rep, algo, name if dt == "f64" else name + "_f32", dominant=dom)
     plan.close()
+    if args.profile_run:
+        return out
     if name == "batch" and not args.no_extras:
         out["extras"] = {"per_grid": batch_vs_per_grid(torch, sgh, xs, lvs)}
     if not args.no_cpu_baseline:
@@ -586,8 +602,8 @@ def secondary_grad(args, torch, np, sgh, W, name):
                                   % (R, "y" if R == 1 else "ies", len(lvs), npts, dt.upper())},
            "kernels": kernel_table(rep, algo),
            "library_kernel_ms_per_step": sum(v["ms"] for v in rep.values()) / args.steps,
-           "roofline": roofline_of(rep, algo, name if R == 1 else "%s_r%d" % (name, R))}
-    if not args.no_cpu_baseline:
+           "roofline": roofline_of(rep, algo, (name if R == 1 else "%s_r%d" % (name, R)) + ("" if dt == "f32" else "_f64"))}
+    if not args.no_cpu_baseline and not args.profile_run:
         import oracle
         xs64 = [a.astype(np.float64) for a in host]
         works = [np.empty_like(x) for x in xs64]
