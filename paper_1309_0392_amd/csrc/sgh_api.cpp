@@ -1041,10 +1041,10 @@ bool medium_task(const Geom &g, MedTask *t) {
 void batch_default_tune(const DevInfo &di, int maxN, int ntasks, int dtype, BatchTune *t, int nt_pref = 0,
                         int persist = -1) {
     // default (what the autotuner picks on MI355X for combination sets): about
-    // 8 FP64 / 16 FP32 elements per thread, 128 to 1024 threads
+    // 16 elements per thread, 128 to 1024 threads
     int nt = nt_pref;
     if (!nt) {
-        const int per = dtype == SGH_F64 ? 8 : 16;
+        const int per = 16;
         nt = std::min(1024, std::max(128, pow2_ceil((maxN + per - 1) / per)));
         if (nt == 1024 && pow2_ceil((maxN + 1023) / 1024) > 8) nt = 512;  // 1024 threads: at most 8 each
     }
