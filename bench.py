@@ -446,8 +446,43 @@ def batch_vs_per_grid(torch, sgh, xs, lv):
            "per_grid_one_call_ms": ms_call, "speedup_vs_per_grid_one_call": ms_call / ms_plan,
            "per_grid_python_loop_ms": ms_loop, "speedup_vs_per_grid_python_loop": ms_loop / ms_plan,
            "plan": plan.describe()["batches"]}
+    res["graph_replay"] = graph_replay(torch, plan, xs)
     plan.close()
     return res
+
+
+def graph_replay(torch, plan, xs):
+    """The plan's launch captured once into a graph (torch.cuda.CUDAGraph) and
+    replayed, beside the direct launch: each of three replays, with eager work
+    and synchronizations between them, must equal a direct execute from the
+    same inputs bit for bit before the replays are timed."""
+    try:
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plan.execute()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            plan.execute()
+        torch.cuda.synchronize()
+        for _ in range(3):
+            before = [t.clone() for t in xs]
+            g.replay()
+            torch.cuda.synchronize()
+            replayed = [t.clone() for t in xs]
+            for t, b in zip(xs, before):
+                t.copy_(b)
+            plan.execute()
+            torch.cuda.synchronize()
+            if not all(bool(torch.equal(a, b)) for a, b in zip(replayed, xs)):
+                return {"error": "a replay differs from the direct launch"}
+        ms = time_region(torch, g.replay, 50) / 50
+        del g
+        return {"ms": ms, "direct_ms_same_run": time_region(torch, plan.execute, 50) / 50, "replays_checked": 3}
+    except Exception as e:  # capture refused by the runtime: report, do not fail the bench
+        return {"error": "%s: %s" % (type(e).__name__, e)}
 
 
 # ------------------------------------------------------- secondary workloads
