@@ -78,6 +78,39 @@ def test_full_size_every_element(name, dtype):
     assert rt <= (1e-14 if dtype == np.float64 else 4e-6)
 
 
+@pytest.mark.parametrize("name", ["aniso3d", "aniso5d"])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_full_size_out_of_place(name, dtype):
+    """The benchmark grids hierarchized out of place in the launch
+    configuration `bench.py --out-of-place` times ((10,9,8): one fused launch
+    with the axis after the walked one folded in), against the whole-grid
+    oracle on every element; the source stays untouched."""
+    if name == "aniso3d":
+        levels, x = W.ANISO_3D, W.sine_plus_noise(W.ANISO_3D, seed=1)
+    else:
+        levels, x = W.ANISO_5D, W.uniform(W.ANISO_5D, seed=2)
+    x = x.astype(dtype)
+    x64 = x.astype(np.float64)
+    sched = sgh.schedule(sgh.OP_HIERARCHIZE, levels, sgh.F64 if dtype == np.float64 else sgh.F32,
+                         out_of_place=True)["launches"]
+    if name == "aniso3d":
+        assert len(sched) == 1 and sched[0]["outer_level"] == 8, sched
+    src = torch.from_numpy(x).cuda()
+    keep = src.clone()
+    dst = torch.empty_like(src)
+    sgh.transform_out(sgh.OP_HIERARCHIZE, src, dst, levels)
+    torch.cuda.synchronize()
+    assert torch.equal(src, keep)
+    del keep
+    got = dst.cpu().numpy()
+    del dst, src
+    ref = ORACLE[sgh.OP_HIERARCHIZE](x64, levels)
+    err = rel_err(sgh.OP_HIERARCHIZE, x64, got, ref)
+    print("full size out of place %s %s (%d launches): max error / max|x| %.3e"
+          % (name, np.dtype(dtype).name, len(sched), err), flush=True)
+    assert err <= TOL[dtype], err
+
+
 def combi(dtype):
     lv, coef = W.combination_set()
     xs = W.combination_values(lv, seed=3, dtype=dtype)
