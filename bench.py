@@ -68,6 +68,8 @@ def parse():
                     help="single grids: the timed step transforms into a second resident buffer (sgh_transform_out)")
     ap.add_argument("--profile-run", action="store_true",
                     help="only the warm-up and the timed steps (no protocol, extras or CPU baseline): for profilers")
+    ap.add_argument("--op", choices=["hierarchize", "dehierarchize", "adjoint"], default="hierarchize",
+                    help="single grids, in place: the operation of the timed steps (default hierarchize)")
     ap.add_argument("--workload", choices=sorted(GRIDS) + sorted(SECONDARY), default="aniso3d")
     return ap.parse_args()
 
@@ -283,9 +285,15 @@ def run_grid(args, torch, np, sgh, W, name):
             tuned[op] = plan.describe()["large"][0]["launches"]
             plan.close()
 
+    step_op = {"hierarchize": sgh.OP_HIERARCHIZE, "dehierarchize": sgh.OP_DEHIERARCHIZE,
+               "adjoint": sgh.OP_ADJOINT}[args.op]
+    if step_op != sgh.OP_HIERARCHIZE and (args.out_of_place or args.autotune):
+        raise SystemExit("--op other than hierarchize: in place and with the default schedule only")
     if args.out_of_place:
         y_out = torch.empty_like(x)
         step = lambda: sgh.transform_out(sgh.OP_HIERARCHIZE, x, y_out, levels)
+    elif step_op != sgh.OP_HIERARCHIZE:
+        step = lambda: sgh.transform(step_op, x, levels)
     else:
         step = lambda: sgh.hierarchize(x, levels)
     for _ in range(args.warmup):
@@ -298,12 +306,19 @@ def run_grid(args, torch, np, sgh, W, name):
     report = sgh.timing_report()
     sgh.timing_enable(False)
     ms = ms_total / args.steps
-    sched = tuned.get(sgh.OP_HIERARCHIZE) or sgh.schedule(sgh.OP_HIERARCHIZE, levels, code,
+    sched = tuned.get(sgh.OP_HIERARCHIZE) or sgh.schedule(step_op, levels, code,
                                                            out_of_place=args.out_of_place)["launches"]
     whole = algo / (ms * 1e-3) / 1e9
     wl = (name if dt == "f64" else name + "_f32") + ("_out" if args.out_of_place else "")
+    if step_op != sgh.OP_HIERARCHIZE:
+        wl += "_" + args.op
+    if step_op == sgh.OP_HIERARCHIZE:
+        metric = METRIC if name == "aniso3d" else "grid points hierarchized/s (%s)" % name
+    else:
+        metric = "grid points %s/s (%s)" % ("dehierarchized" if step_op == sgh.OP_DEHIERARCHIZE else
+                                              "transformed by the adjoint", name)
     out = {
-        "metric": METRIC if name == "aniso3d" else "grid points hierarchized/s (%s)" % name,
+        "metric": metric,
         "value": N / (ms * 1e-3), "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
         "data": "synthetic",
@@ -317,7 +332,9 @@ def run_grid(args, torch, np, sgh, W, name):
     }
     if args.out_of_place:
         out["config"]["workload"] += ", out of place into a second resident buffer"
-    if args.profile_run:
+    if step_op != sgh.OP_HIERARCHIZE:
+        out["config"]["workload"] += ", operation: " + args.op
+    if args.profile_run or step_op != sgh.OP_HIERARCHIZE:
         return out
     out["timing_protocol"] = protocol(torch, step, lambda: sgh.dehierarchize(x, levels))
     out["timing_protocol"]["points_per_s_median"] = N / (out["timing_protocol"]["forward"]["median_ms"] * 1e-3)
