@@ -680,7 +680,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the transform of one grid, or of a combination set, "
-              "runs on a single device here (multi-GPU sharding is described in DESIGN.md, not built); "
+              "runs on a single device here (sharding across GPUs is not built); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
